@@ -1,0 +1,182 @@
+"""Benchmark: the fused BGK step on one MI355X.
+
+Workload (default): D2Q37 velocity set, 4th-order Hermite equilibrium, periodic 4096 x 4096
+grid, decaying standing shear wave u_x = 1e-3 sin(2 pi y / 4096) with uniform density noise
+1e-6 (seed 1), Kn = 0.1, populations stored as FP32 deviations from w_a rho0, FP32 collision.
+A step is one launch of the fused shift-moments-equilibrium-relaxation kernel over every
+cell.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--variants]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and HBM GB/s (% roofline), BF16/FP32 vs FP64 at stated decay error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("bgk_device.h", "kernels_impl.h", "kernels.h", "lattices.inc"):
+        with open(os.path.join(ROOT, "paper_0908_4520_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag: str, per_launch_algorithmic: float):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the
+    current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(kernel_tag)
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_steps(sim, steps, stream, torch):
+    """Average launch duration (ms) over `steps` launches, with HIP events recorded on the
+    stream the kernels are launched on."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, warmup, sr=False, noise=0.0):
+    n_w = grid[axis]
+    tau = lbm.lbm_tau_from_kn(lattice, kn, n_w)
+    with lbm.Sim(lattice, N, tau, grid, storage=storage, stream=stream.cuda_stream, stochastic_round=sr,
+                 sr_seed=12345) as s:
+        s.set_shear_wave(1e-3, axis, rho_noise=noise, seed=1)
+        tile, _ = s.autotune(3)
+        s.set_shear_wave(1e-3, axis, rho_noise=noise, seed=1)
+        s.step(warmup)
+        ms = time_steps(s, steps, stream, torch)
+        mlups = s.ncell / (ms * 1e-3) / 1e6
+        gbs = s.bytes_per_step / (ms * 1e-3) / 1e9
+        return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, frac=gbs / HBM_PEAK_GBS, tile=tile,
+                    bytes_per_step=s.bytes_per_step, ncell=s.ncell)
+
+
+def cpu_baseline(target_seconds=12.0):
+    """The FP64 oracle on a bounded sample of the workload: D2Q37, N = 4, Kn = 0.1 on a
+    4096 x 256 slab of the 4096 x 4096 grid (same wave, noise and tau), whole steps."""
+    import numpy as np  # noqa: F401
+    from oracle import bgk as ob
+    grid = (4096, 256, 1)
+    tau = ob.tau_from_kn(ob.lattices.get("D2Q37"), 0.1, 4096)
+    sim = ob.BGK("D2Q37", 4, tau, grid)
+    sim.set_shear_wave(1e-3, 1, rho_noise=1e-6, seed=1)
+    t0 = time.perf_counter()
+    sim.step(1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(50, int(target_seconds / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    cores = ob.lib().orc_max_threads()
+    return {"value": sim.ncell * steps / dt / 1e6, "unit": "MLUPS", "cores": int(cores), "kind": "oracle",
+            "sample": f"D2Q37 N=4 FP64, 4096x256 slab of the 4096x4096 workload, {steps} steps "
+                      f"({dt:.1f} s), OpenMP over cells"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true", help="also time the other storages and sets")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_0908_4520_amd import lbm
+    stream = torch.cuda.current_stream()
+
+    log("timing D2Q37 4096x4096 N=4 fp32_dev ...")
+    main_res = run_variant(lbm, torch, stream, "D2Q37", 4, 0.1, (4096, 4096, 1), "fp32_dev", 1,
+                           args.steps, args.warmup, noise=1e-6)
+    log(f"  {main_res['ms_per_step']:.4f} ms/step, {main_res['mlups']:.0f} MLUPS, {main_res['gbs']:.0f} GB/s")
+
+    variants = {}
+    if args.variants:
+        for name, kw in [
+            ("D3Q39_512^3_fp32_dev", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp32_dev", axis=2)),
+            ("D3Q39_512^3_bf16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="bf16_dev", axis=2, sr=True)),
+            ("D3Q39_512^3_fp16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp16_dev", axis=2, sr=True)),
+            ("D2Q16-GH_2048^2_fp32_dev", dict(lattice="D2Q16-GH", N=3, kn=1.0, grid=(2048, 2048, 1), storage="fp32_dev", axis=1)),
+            ("D2Q37_4096^2_fp32", dict(lattice="D2Q37", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32", axis=1, noise=1e-6)),
+        ]:
+            log(f"timing {name} ...")
+            r = run_variant(lbm, torch, stream, steps=min(args.steps, 200), warmup=5, **kw)
+            variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+            log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS, {r['gbs']:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample ...")
+        cpu = cpu_baseline()
+        log(f"  {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+
+    ms = main_res["ms_per_step"]
+    achieved = main_res["bytes_per_step"] / (ms * 1e-3) / 1e9
+    tag = "k_shift_rows<D2Q37,4,fp32_dev>@4096x4096"
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q37 N=4 shear wave 4096x4096, Kn=0.1, rho noise 1e-6 seed 1, FP32 deviation storage",
+                   "lattice": "D2Q37", "eq_order": 4, "grid": [4096, 4096, 1], "storage": "fp32_dev",
+                   "tile": main_res["tile"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profiles(tag, main_res["bytes_per_step"]),
+                     "kernel": tag, "algorithmic_bytes_per_launch": main_res["bytes_per_step"]},
+        "cpu_baseline": cpu,
+    }
+    if variants:
+        out["variants"] = variants
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) BGK step for high-order lattice Boltzmann (LB)
+ * and discrete-velocity (DVM) models.
+ *
+ * Method (Meng & Zhang, "Accuracy analysis of high-order lattice Boltzmann models for
+ * rarefied gas flows"): populations f_a of a Gauss-Hermite velocity set {xi_a, w_a}
+ * (section 2.1, Eqs. approxf, an, lbgk; Table 1) evolve by the second-order BGK scheme
+ * of section 2.2 (Eq. 2order).  One time step, fused in one kernel per step:
+ *   move      f_a(r) = f*_a(r - c_a)  -- exact periodic shift for integer (on-lattice)
+ *             velocity sets (Eq. slb, Eq. 2order), or second-order upwind (Beam-Warming)
+ *             advection per axis for off-lattice Gauss-Hermite sets (section 3.2);
+ *   moments   rho = sum_a f_a, rho u = sum_a xi_a f_a                 (Eq. an, n = 0, 1);
+ *   f^eq_a    = w_a rho sum_{n<=N} He_n-terms of (xi_a.u, u.u)        (Eq. demoeq for N=2;
+ *             general N from a_eq^(n) = rho u^n, section 2.1);
+ *   relax     f*_a = f_a - omega (f_a - f^eq_a), omega = 1/tau, tau = Kn/dt + 1/2.
+ * The state kept between steps is the post-collision population f*.
+ *
+ * Units.  Velocities are in Hermite units (scaled by sqrt(R T0), Eq. nondime).  Grid cells
+ * are unit spaced; on-lattice sets move c_a = xi_a / scale cells per step; off-lattice sets
+ * advect with Courant numbers nu_ad = xi_ad * cfl / max_ad|xi_ad|.
+ *
+ * Layout.  cell = x + nx*(y + ny*z); populations are structure-of-arrays: every host array
+ * of populations is f[a * ncell + cell] in FP64, in the population order reported by
+ * lbm_lattice_info.  Per-cell vectors are u[d * ncell + cell].
+ *
+ * Errors.  Every call returns lbm_status; nothing throws or aborts across the ABI.  On an
+ * error lbm_last_error() returns a thread-local message.  Output arguments are written only
+ * on LBM_OK.  Host pointers are borrowed for the duration of the call only.
+ *
+ * Streams.  Work is enqueued on the simulation's HIP stream (the null stream unless one is
+ * given in lbm_opts).  lbm_step is asynchronous; calls that return host data synchronise
+ * that stream first.  One simulation must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* an argument is out of range; nothing was changed */
+    LBM_ENOMEM = -2,     /* device (or pinned host) allocation failed */
+    LBM_EDEVICE = -3,    /* a HIP call failed; lbm_last_error() has the HIP message */
+    LBM_ENONFINITE = -4, /* the finite check found a NaN/Inf in the state */
+    LBM_ESTATE = -5      /* the call is not valid in the object's current state */
+} lbm_status;
+
+/* Velocity sets.  Degrees are those of polynomial exactness of the quadrature. */
+typedef enum {
+    LBM_D2Q9 = 1,     /* Table 1; degree 5; |c| <= 1 */
+    LBM_D2Q37 = 2,    /* 9th-degree on-lattice set, shells (0,0)..(3,1); |c| <= 3 */
+    LBM_D3Q39 = 3,    /* 7th-degree on-lattice set, r^2 = 3/2; |c| <= 3 */
+    LBM_D2Q16_GH = 4, /* 4x4 Gauss-Hermite product, off-lattice; degree 7 */
+    LBM_D2Q36_GH = 5, /* 6x6 Gauss-Hermite product, off-lattice; degree 11 */
+    LBM_D2Q16_CK = 6, /* Table 1 D2Q16 (m=1, n=4); degree 5 with these integers; |c| <= 4 */
+    LBM_D2Q17 = 7,    /* Table 1; degree 7; |c| <= 3 */
+    LBM_D2Q21 = 8,    /* Table 1; degree 7; |c| <= 3 */
+    LBM_D2Q25_CK = 9  /* Table 1 D2Q25 (m=3, n=7); degree 7 with these integers; |c| <= 7 */
+} lbm_lattice;
+
+/* How populations are stored in device memory between steps.  The collision runs in FP64
+ * for LBM_FP64 and in FP32 for every other storage.  *_DEV stores the deviation
+ * g_a = f_a - w_a rho0 (rho0 = 1); LBM_FP16_DEV stores g_a / w_a. */
+typedef enum {
+    LBM_FP64 = 0,
+    LBM_FP32 = 1,
+    LBM_FP32_DEV = 2,
+    LBM_FP16_DEV = 3,
+    LBM_BF16_DEV = 4
+} lbm_storage;
+
+/* How to move populations each step. */
+typedef enum {
+    LBM_MOVE_AUTO = 0,  /* SHIFT for on-lattice sets, BW2 for off-lattice sets */
+    LBM_MOVE_SHIFT = 1, /* exact periodic shift by c_a (on-lattice sets only) */
+    LBM_MOVE_BW2 = 2    /* Beam-Warming second-order upwind advection, x then y then z */
+} lbm_move;
+
+typedef struct { int32_t nx, ny, nz; } lbm_grid;   /* nz = 1 for 2-D velocity sets */
+
+typedef struct {
+    lbm_storage storage;      /* default LBM_FP64 */
+    lbm_move move;            /* default LBM_MOVE_AUTO */
+    double cfl;               /* largest Courant number for LBM_MOVE_BW2, in (0, 1]; default 0.5 */
+    int32_t stochastic_round; /* 16-bit storages: 0 = round to nearest even, 1 = stochastic */
+    uint64_t sr_seed;         /* seed of the stochastic rounding stream */
+    void *hip_stream;         /* hipStream_t to enqueue on; NULL = null stream */
+    int32_t check_every;      /* >0: lbm_step checks the state for NaN/Inf every this many steps */
+    int32_t tile;             /* kernel tile choice (0 = autotuned / default); see lbm_tile_count */
+} lbm_opts;
+
+typedef struct lbm_sim lbm_sim;
+
+/* Fill *o with the defaults listed above. */
+void lbm_opts_default(lbm_opts *o);
+
+/* Velocity-set description in the library's population order.  Q and D are written when
+ * non-NULL; c (Q*3 ints, zero third component in 2-D, all zero for off-lattice sets),
+ * xi (Q*3 doubles, Hermite units) and w (Q doubles) are written when non-NULL.
+ * Returns LBM_EINVAL for an unknown lattice. */
+lbm_status lbm_lattice_info(lbm_lattice lat, int32_t *Q, int32_t *D, int32_t *c, double *xi, double *w);
+
+/* Relaxation time for a Knudsen number (Eq. 2order: omega = dt/(Kn + dt/2) = 1/tau).
+ * The characteristic length of Eq. nondime is one wavelength over wavelength_cells cells,
+ * theta = 2 pi / wavelength_cells, so dx = 2 pi / wavelength_cells; dt = dx / scale for
+ * on-lattice sets (xi_a dt = c_a dx) and dt = cfl dx / max|xi| for advection.
+ * Returns tau = Kn/dt + 1/2, or NaN for invalid arguments. */
+double lbm_tau_from_kn(lbm_lattice lat, lbm_move move, double kn, int32_t wavelength_cells, double cfl);
+
+/* Create a simulation with the default options.  eq_order N in 1..4; tau > 1/2 (INFINITY
+ * means collisionless, omega = 0); every grid dimension >= 1; nz = 1 for 2-D sets.
+ * Allocates two population buffers on the current HIP device.  The state is zero until
+ * one of the set calls below.  A quadrature degree below 2N (section 2.1) is allowed;
+ * lbm_warnings() then reports LBM_WARN_QUADRATURE. */
+lbm_status lbm_init(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g);
+lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g,
+                       const lbm_opts *o);
+void lbm_free(lbm_sim *s);   /* NULL-safe; synchronises the stream first */
+
+#define LBM_WARN_QUADRATURE 1u
+uint32_t lbm_warnings(const lbm_sim *s);
+
+/* Standing shear wave of section 4 without forcing, at equilibrium (f = f^eq, step 0):
+ * u_x = u0 sin(2 pi j / N_w) with j the cell index along wave_axis (1 = y, 2 = z) and
+ * N_w that axis' length; u_y = u_z = 0; rho = 1 + rho_noise (2U - 1) with
+ * U = (h >> 11) 2^-53 and h = SplitMix64 output number cell+1 of the stream started at
+ * seed.  Runs on the device; asynchronous. */
+lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double rho_noise, uint64_t seed);
+
+/* f = f^eq(rho, u) from host fields rho[ncell], u[D*ncell]; resets the step counter. */
+lbm_status lbm_init_equilibrium(lbm_sim *s, const double *rho, const double *u);
+
+/* Advance n >= 0 steps (asynchronous).  With check_every > 0 the state is checked for
+ * non-finite values every check_every steps and LBM_ENONFINITE returned on the first hit. */
+lbm_status lbm_step(lbm_sim *s, int64_t n);
+
+/* Number of steps taken since the last set call. */
+int64_t lbm_step_count(const lbm_sim *s);
+
+/* Host copies (synchronising): rho[ncell] and u[D*ncell] in FP64 from the stored f*
+ * (the collision conserves rho and rho u, so these are the moments at the current step). */
+lbm_status lbm_moments(lbm_sim *s, double *rho, double *u);
+
+/* Sine and cosine projections of the x-velocity along wave_axis, in FP64:
+ * a_sin = (2/N_w) sum_j ubar_x(j) sin(2 pi j/N_w), ubar_x(j) the mean of u_x over the cells
+ * with wave-axis index j (the velocity amplitude of section 4); a_cos likewise. */
+lbm_status lbm_shear_amplitude(lbm_sim *s, int32_t wave_axis, double *a_sin, double *a_cos);
+
+/* Global FP64 sums: mass = sum rho, mom[d] = sum rho u_d (D entries). */
+lbm_status lbm_totals(lbm_sim *s, double *mass, double *mom);
+
+/* Decoded FP64 copy of the stored state f*[a * ncell + cell] (checkpoint), and its inverse
+ * (encodes into the storage format, rounding as configured; resets nothing else). */
+lbm_status lbm_get_populations(lbm_sim *s, double *f);
+lbm_status lbm_set_populations(lbm_sim *s, const double *f);
+/* Restore the step counter together with lbm_set_populations (checkpoint resume). */
+lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
+
+/* Raw checkpoint of the stored state in its storage format (bit-exact restore):
+ * lbm_state_bytes gives the size; save copies the current buffer to host memory, load copies
+ * it back.  Together with lbm_step_count / lbm_set_step_count this resumes a run exactly. */
+lbm_status lbm_state_bytes(const lbm_sim *s, int64_t *bytes);
+lbm_status lbm_save_state(lbm_sim *s, void *host, int64_t bytes);
+lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes);
+
+/* Least-squares slope of -ln|amp[k]| against steps[k] over n_first <= steps[k] <= n_last,
+ * in FP64 (the decay rate per step of the shear-wave amplitude).  Needs >= 2 points. */
+lbm_status lbm_fit_decay(const double *amp, const int64_t *steps, int64_t count, int64_t n_first,
+                         int64_t n_last, double *gamma);
+
+/* Tile choices of the step kernel for this simulation's configuration; lbm_set_tile picks one
+ * (0 = default), lbm_autotune times every choice on a scratch copy of the state and keeps the
+ * fastest (the state itself is left unchanged). */
+int32_t lbm_tile_count(const lbm_sim *s);
+lbm_status lbm_set_tile(lbm_sim *s, int32_t tile);
+lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile, double *best_ms);
+
+/* Information: cells, populations and bytes moved per step (2 Q ncell * bytes per value). */
+lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, int64_t *bytes_per_step);
+
+/* Thread-local text of the last error (empty string if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

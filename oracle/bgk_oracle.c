@@ -179,3 +179,10 @@ void orc_moments(int Q, int D, const double *xi, long ncell, const double *f, do
 }
 
 int orc_max_q(void) { return ORC_MAXQ; }
+
+#ifdef _OPENMP
+#include <omp.h>
+int orc_max_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_max_threads(void) { return 1; }
+#endif

@@ -1,0 +1,220 @@
+// bgk_device.h -- device building blocks of the BGK step: storage codec, moment
+// projection, N-th order Hermite equilibrium and relaxation, fused per cell.
+//
+// Stored value v_a of population a ("v-space"):
+//   full storages (FP64, FP32):  v_a = f_a
+//   deviation storages (*_DEV):  v_a = f_a - w_a rho0,      rho0 = 1
+//   scaled deviation (FP16_DEV): v_a = (f_a - w_a rho0) / w_a
+// so f_a - a_a = m_a v_a with a_a = w_a rho0 [dev], m_a = w_a [scaled] or 1.
+//
+// Collision (paper, section 2.2, Eq. 2order, with the moments of Eq. an and the
+// Hermite equilibrium of Eq. demoeq generalised to order N <= 4):
+//   d = sum_a m_a v_a  (= rho, or rho - rho0 for deviations),  j = sum_a xi_a m_a v_a,
+//   rho = rho0 [dev] + d,  u = j / rho,  q = u.u,  s_a = xi_a.u,
+//   f^eq_a = w_a rho P_N(s_a, q),
+//   P_N = 1 + s + (s^2 - q)/2 + (s^3 - 3 s q)/6 + (s^4 - 6 s^2 q + 3 q^2)/24 (truncated),
+//   f*_a = f_a - omega (f_a - f^eq_a).
+// In v-space, with e_a = w_a (or 1 when scaled):
+//   v*_a = (1 - omega) v_a + omega e_a (d + rho (P_N(s_a) - 1)),
+// and P_N - 1 is the polynomial a0' + a1 s + a2 s^2 + a3 s^3 + a4 s^4 whose coefficients
+// depend only on q, so each population costs one dot product and a Horner chain.
+// With omega = 0 every term added to v_a is an exact zero, so a collisionless step moves
+// the stored values bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lattices.inc"
+
+namespace lbm {
+
+enum Storage : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3, ST_BF16_DEV = 4 };
+
+// ------------------------------------------------------------------ compile-time loop
+template <int I>
+using ic = std::integral_constant<int, I>;
+
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(ic<Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ------------------------------------------------------------------ random bits
+// 32-bit integer finaliser (xorshift-multiply, "lowbias32" constants by C. Wellons).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// ------------------------------------------------------------------ storage codec
+template <int S>
+struct Codec;
+
+template <>
+struct Codec<ST_FP64> {
+    using raw = double;
+    using T = double;
+    static constexpr bool dev = false, scaled = false, lowp = false;
+    __device__ static T dec(raw r) { return r; }
+    __device__ static double dec64(raw r) { return r; }
+    template <bool SR>
+    __device__ static raw enc(T v, uint32_t) { return v; }
+};
+
+template <>
+struct Codec<ST_FP32> {
+    using raw = float;
+    using T = float;
+    static constexpr bool dev = false, scaled = false, lowp = false;
+    __device__ static T dec(raw r) { return r; }
+    __device__ static double dec64(raw r) { return (double)r; }
+    template <bool SR>
+    __device__ static raw enc(T v, uint32_t) { return v; }
+};
+
+template <>
+struct Codec<ST_FP32_DEV> : Codec<ST_FP32> {
+    static constexpr bool dev = true;
+};
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+template <>
+struct Codec<ST_BF16_DEV> {
+    using raw = uint16_t;
+    using T = float;
+    static constexpr bool dev = true, scaled = false, lowp = true;
+    __device__ static T dec(raw r) { return __builtin_bit_cast(float, (uint32_t)r << 16); }
+    __device__ static double dec64(raw r) { return (double)dec(r); }
+    template <bool SR>
+    __device__ static raw enc(T v, uint32_t rnd) {
+        if constexpr (SR) {
+            bf16x2 p = {};
+            p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v, rnd, false);
+            return __builtin_bit_cast(uint16_t, p[0]);
+        } else {
+            return __builtin_bit_cast(uint16_t, (__bf16)v);   // round to nearest even
+        }
+    }
+};
+
+template <>
+struct Codec<ST_FP16_DEV> {
+    using raw = uint16_t;
+    using T = float;
+    static constexpr bool dev = true, scaled = true, lowp = true;
+    __device__ static T dec(raw r) { return (float)__builtin_bit_cast(_Float16, r); }
+    __device__ static double dec64(raw r) { return (double)dec(r); }
+    template <bool SR>
+    __device__ static raw enc(T v, uint32_t rnd) {
+        if constexpr (SR) {
+            f16x2 p = {};
+            p = __builtin_amdgcn_cvt_sr_f16_f32(p, v, rnd, false);
+            return __builtin_bit_cast(uint16_t, p[0]);
+        } else {
+            return __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
+        }
+    }
+};
+
+// m_a: factor from stored value to f_a - a_a; e_a: factor from (f^eq_a - a_a)/w_a to v-space.
+template <class L, int S, int A>
+__device__ __forceinline__ constexpr double moment_factor() {
+    return Codec<S>::scaled ? L::w[A] : 1.0;
+}
+template <class L, int S, int A>
+__device__ __forceinline__ constexpr double eq_factor() {
+    return Codec<S>::scaled ? 1.0 : L::w[A];
+}
+
+// ------------------------------------------------------------------ moments + collision
+template <class T>
+struct Moments {
+    T d, jx, jy, jz;
+};
+
+template <class L, int S, class T>
+__device__ __forceinline__ Moments<T> project(const T (&v)[L::Q]) {
+    Moments<T> m{T(0), T(0), T(0), T(0)};
+    static_for<L::Q>([&](auto I) {
+        constexpr int a = decltype(I)::value;
+        constexpr double mf = moment_factor<L, S, a>();
+        const T g = (mf == 1.0) ? v[a] : T(mf) * v[a];
+        m.d += g;
+        if constexpr (L::xi[a][0] != 0.0) m.jx += T(L::xi[a][0]) * g;
+        if constexpr (L::xi[a][1] != 0.0) m.jy += T(L::xi[a][1]) * g;
+        if constexpr (L::D == 3 && L::xi[a][2] != 0.0) m.jz += T(L::xi[a][2]) * g;
+    });
+    return m;
+}
+
+// Relax the Q values in place; omega = 1/tau (0 = collisionless).
+template <class L, int N, int S, class T>
+__device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
+    static_assert(N >= 1 && N <= 4, "Hermite order 1..4");
+    const Moments<T> m = project<L, S>(v);
+    const T rho = Codec<S>::dev ? T(1) + m.d : m.d;
+    const T inv = T(1) / rho;
+    const T ux = m.jx * inv, uy = m.jy * inv, uz = (L::D == 3) ? m.jz * inv : T(0);
+    const T q = ux * ux + uy * uy + uz * uz;
+    // P_N(s) - 1 = a0m + a1 s + a2 s^2 + a3 s^3 + a4 s^4
+    T a0m = T(0), a1 = T(1), a2 = T(0);
+    if constexpr (N >= 2) { a0m = T(-0.5) * q; a2 = T(0.5); }
+    if constexpr (N >= 3) { a1 = T(1) - T(0.5) * q; }
+    if constexpr (N >= 4) { a0m = q * (T(0.125) * q - T(0.5)); a2 = T(0.5) - T(0.25) * q; }
+    const T orho = omega * rho;
+    const T B0 = omega * (m.d + rho * a0m);
+    const T B1 = orho * a1;
+    const T B2 = orho * a2;
+    const T B3 = orho * T(1.0 / 6.0);
+    const T B4 = orho * T(1.0 / 24.0);
+    const T keep = T(1) - omega;
+    static_for<L::Q>([&](auto I) {
+        constexpr int a = decltype(I)::value;
+        T s = T(0);
+        if constexpr (L::xi[a][0] != 0.0) s += T(L::xi[a][0]) * ux;
+        if constexpr (L::xi[a][1] != 0.0) s += T(L::xi[a][1]) * uy;
+        if constexpr (L::D == 3 && L::xi[a][2] != 0.0) s += T(L::xi[a][2]) * uz;
+        T p;
+        if constexpr (N == 1) p = B1;
+        if constexpr (N == 2) p = B1 + s * B2;
+        if constexpr (N == 3) p = B1 + s * (B2 + s * B3);
+        if constexpr (N == 4) p = B1 + s * (B2 + s * (B3 + s * B4));
+        p = B0 + s * p;
+        constexpr double ef = eq_factor<L, S, a>();
+        v[a] = (ef == 1.0) ? keep * v[a] + p : keep * v[a] + T(ef) * p;
+    });
+}
+
+// ------------------------------------------------------------------ equilibrium (init)
+// v-space equilibrium values for given rho, u (FP64), used to initialise and encode.
+template <class L, int N, int S>
+__device__ __forceinline__ void equilibrium_v(double rho, double ux, double uy, double uz,
+                                              double (&out)[L::Q]) {
+    const double q = ux * ux + uy * uy + uz * uz;
+    const double d = Codec<S>::dev ? rho - 1.0 : rho;
+    static_for<L::Q>([&](auto I) {
+        constexpr int a = decltype(I)::value;
+        const double s = L::xi[a][0] * ux + L::xi[a][1] * uy + L::xi[a][2] * uz;
+        double pm1 = s;   // P_N - 1, term by term
+        if constexpr (N >= 2) pm1 += 0.5 * (s * s - q);
+        if constexpr (N >= 3) pm1 += (s * s * s - 3.0 * s * q) / 6.0;
+        if constexpr (N >= 4) pm1 += (s * s * s * s - 6.0 * s * s * q + 3.0 * q * q) / 24.0;
+        out[a] = eq_factor<L, S, a>() * (d + rho * pm1);
+    });
+}
+
+}  // namespace lbm

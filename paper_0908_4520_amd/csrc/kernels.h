@@ -1,0 +1,108 @@
+// kernels.h -- interface between the host runtime and the per-lattice kernel units.
+//
+// Each lattice unit (k_<lattice>.hip) instantiates the templates of kernels_impl.h for
+// its velocity set and fills a table of host launchers; the runtime (api.cpp) picks the
+// entry for a simulation's (lattice, Hermite order, storage, rounding).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace lbm {
+
+constexpr int kMaxQ = 40;       // largest Q of any supported set (D3Q39)
+constexpr int kBlock = 256;     // threads per workgroup of every step kernel
+
+// Arguments shared by the step kernels (passed by value as kernel arguments).
+struct StepArgs {
+    const void *fin;
+    void *fout;
+    int32_t nx, ny, nz;
+    uint32_t pstride;      // elements between consecutive population planes
+    uint32_t per_row;      // shift rows kernel: blocks per row; bw2: blocks per strip row
+    uint32_t tile;         // shift rows kernel: 256-cell chunks per block; bw2: rows per strip
+    uint32_t nblocks;      // grid size (1-D)
+    uint32_t sr_key;       // per-step key of the stochastic-rounding stream
+    double omega;          // 1/tau (0 = collisionless)
+};
+
+// Beam-Warming coefficients per population and axis: g = f - alpha D1 + beta D2 with
+// alpha = a + a(1-a)/2, beta = a(1-a)/2, a = |nu| (D1, D2 the one-sided differences).
+template <class T>
+struct BWCoef {
+    T alpha[2][kMaxQ];
+    T beta[2][kMaxQ];
+};
+
+struct WaveArgs {
+    void *f;
+    int32_t nx, ny, nz;
+    uint32_t pstride;
+    int32_t wave_axis;
+    double u0, rho_noise;
+    uint64_t seed;
+    const double *sin_tab;   // sin(2 pi j / N_w), j = 0..N_w-1 (host libm)
+};
+
+struct DiagArgs {
+    const void *f;
+    int32_t nx, ny, nz;
+    uint32_t pstride;
+    int32_t wave_axis;
+    const double *sin_tab, *cos_tab;
+    double *partials;        // [nblocks][6]: sum u_x sin, sum u_x cos, sum d, sum j_x, j_y, j_z
+};
+
+using StepFn = hipError_t (*)(const StepArgs &, hipStream_t);
+using StepBW32 = hipError_t (*)(const StepArgs &, const BWCoef<float> &, hipStream_t);
+using StepBW64 = hipError_t (*)(const StepArgs &, const BWCoef<double> &, hipStream_t);
+using WaveFn = hipError_t (*)(const WaveArgs &, hipStream_t);
+using FieldsFn = hipError_t (*)(void *f, uint32_t pstride, uint32_t ncell, const double *rho,
+                                const double *u, hipStream_t);
+using DecodeFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, int a, double add,
+                                double mul, double *out, hipStream_t);
+using EncodeFn = hipError_t (*)(void *f, uint32_t pstride, uint32_t ncell, int a, double add,
+                                double scale, const double *in, uint32_t sr_key, hipStream_t);
+using MomentsFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, double *rho,
+                                 double *u, hipStream_t);
+using DiagFn = hipError_t (*)(const DiagArgs &, uint32_t nblocks, hipStream_t);
+using FiniteFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, int Q, int *flag,
+                                hipStream_t);
+
+// Everything for one (lattice, N, storage, rounding) combination.
+struct KernelSet {
+    int lattice, order, storage, sr;
+    StepFn shift_rows;     // on-lattice shift, row tiles (needs nx, ny, nz >= R)
+    StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
+    StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
+    StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision
+    WaveFn init_wave;
+    FieldsFn init_fields;
+    DecodeFn decode;
+    EncodeFn encode;
+    MomentsFn moments;
+    DiagFn diag;
+    FiniteFn finite;
+};
+
+std::vector<KernelSet> &registry();
+
+void register_D2Q9();
+void register_D2Q37();
+void register_D3Q39();
+void register_D2Q16_GH();
+void register_D2Q36_GH();
+void register_D2Q16_CK();
+void register_D2Q17();
+void register_D2Q21();
+void register_D2Q25_CK();
+
+// Zero n ints with a kernel (kept out of hipMemsetAsync so the step path can be captured).
+hipError_t fill_zero(int *p, uint32_t n, hipStream_t s);
+
+// Fixed-order final reduction of DiagFn partials: out[k] = sum_b partials[b][k], k < 6.
+hipError_t diag_final(const double *partials, uint32_t nblocks, double *out, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,443 @@
+// kernels_impl.h -- kernel templates, included by the per-lattice units only.
+#pragma once
+
+#include <math.h>
+
+#include "bgk_device.h"
+#include "kernels.h"
+
+namespace lbm {
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b mod 8).  When
+// the grid divides evenly, give each XCD a contiguous range of logical tiles so that the
+// tiles sharing halo cache lines meet in the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
+    return (nblocks & 7u) == 0u ? (bid & 7u) * (nblocks >> 3) + (bid >> 3) : bid;
+}
+
+// Per-population stochastic-rounding bits from one hash per cell.
+__device__ __forceinline__ uint32_t pop_bits(uint32_t cell_hash, int a) {
+    return mix32(cell_hash + 0x9e3779b9u * (uint32_t)(a + 1));
+}
+
+__device__ __forceinline__ int wrap_once(int v, int n) {   // |v| < 2n
+    v += (v < 0) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+__device__ __forceinline__ int imod(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------- exact shift, row tiles
+// Block = `tile` chunks of 256 consecutive cells of one row (y, z).  Thread pulls
+// f*_a(x - c_a) for every a, collides, and writes f*(x) to the other buffer.  Loads of one
+// population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned.
+template <class L, int N, int S, bool SR>
+__global__ __launch_bounds__(kBlock) void k_shift_rows(StepArgs a) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    using T = typename C::T;
+    const uint32_t lb = xcd_tile(blockIdx.x, a.nblocks);
+    const uint32_t row = lb / a.per_row;
+    const uint32_t xb = lb - row * a.per_row;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+    raw *__restrict__ fout = static_cast<raw *>(a.fout);
+    const size_t ps = a.pstride;
+    const T om = (T)a.omega;
+    for (uint32_t k = 0; k < a.tile; ++k) {
+        const int x = (int)((xb * a.tile + k) * kBlock + threadIdx.x);
+        if (x >= nx) break;
+        T v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            int ys = y - cy, zs = z - cz;
+            if constexpr (cy > 0) ys += (ys < 0) ? ny : 0;
+            if constexpr (cy < 0) ys -= (ys >= ny) ? ny : 0;
+            if constexpr (cz > 0) zs += (zs < 0) ? nz : 0;
+            if constexpr (cz < 0) zs -= (zs >= nz) ? nz : 0;
+            int xs = x - cx;
+            if constexpr (cx > 0) xs += (xs < 0) ? nx : 0;
+            if constexpr (cx < 0) xs -= (xs >= nx) ? nx : 0;
+            const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * (size_t)nx;
+            v[i] = C::dec(p[xs]);
+        });
+        collide<L, N, S, T>(v, om);
+        const size_t o = (size_t)row * (size_t)nx + (size_t)x;
+        const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+        });
+    }
+}
+
+// ---------------------------------------------------------------- exact shift, any grid
+template <class L, int N, int S, bool SR>
+__global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    using T = typename C::T;
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x = (int)(cell % (uint32_t)nx);
+    const uint32_t t = cell / (uint32_t)nx;
+    const int y = (int)(t % (uint32_t)ny), z = (int)(t / (uint32_t)ny);
+    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+    raw *__restrict__ fout = static_cast<raw *>(a.fout);
+    const size_t ps = a.pstride;
+    T v[L::Q];
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny), zs = imod(z - L::c[i][2], nz);
+        v[i] = C::dec(fin[(size_t)i * ps + (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs)]);
+    });
+    collide<L, N, S, T>(v, (T)a.omega);
+    const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        fout[(size_t)i * ps + cell] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+    });
+}
+
+// ---------------------------------------------------------------- Beam-Warming, 2-D
+// Thread = one column x walking a strip of `tile` rows.  For each population it keeps the
+// x-advected values of the two upwind rows in registers (sliding window), so every row of
+// every population is x-advected once per strip, plus two halo rows.  The x-neighbours
+// x - s, x - 2s come from neighbouring lanes' loads through L1.
+template <class L, int N, int S, bool SR, class T>
+__global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
+    static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    const uint32_t lb = xcd_tile(blockIdx.x, a.nblocks);
+    const uint32_t strip = lb / a.per_row;
+    const uint32_t xb = lb - strip * a.per_row;
+    const int nx = a.nx, ny = a.ny;
+    const int x = (int)(xb * kBlock + threadIdx.x);
+    if (x >= nx) return;
+    const int y0 = (int)(strip * a.tile);
+    const int y1 = min(y0 + (int)a.tile, ny);
+    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+    raw *__restrict__ fout = static_cast<raw *>(a.fout);
+    const size_t ps = a.pstride;
+    // wrapped neighbour columns (nx may be 1 or 2: wrap twice)
+    const int xm1 = wrap_once(wrap_once(x - 1, nx), nx), xm2 = wrap_once(wrap_once(x - 2, nx), nx);
+    const int xp1 = wrap_once(wrap_once(x + 1, nx), nx), xp2 = wrap_once(wrap_once(x + 2, nx), nx);
+    auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * (size_t)nx; };
+    auto xadv = [&](auto I, size_t roff) -> T {
+        constexpr int i = decltype(I)::value;
+        constexpr bool px = L::xi[i][0] > 0.0;
+        const raw *p = fin + (size_t)i * ps + roff;
+        const T f0 = (T)C::dec(p[x]);
+        const T f1 = (T)C::dec(p[px ? xm1 : xp1]);
+        const T f2 = (T)C::dec(p[px ? xm2 : xp2]);
+        return f0 - cf.alpha[0][i] * (f0 - f1) + cf.beta[0][i] * (f1 - f2);
+    };
+    T A[L::Q], B[L::Q];
+    {
+        const size_t rm2 = row_of(y0 - 2), rm1 = row_of(y0 - 1), r0 = row_of(y0), rp1 = row_of(y0 + 1);
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (L::xi[i][1] > 0.0) {
+                A[i] = xadv(I, rm2);
+                B[i] = xadv(I, rm1);
+            } else {
+                A[i] = xadv(I, r0);
+                B[i] = xadv(I, rp1);
+            }
+        });
+    }
+    const T om = (T)a.omega;
+    for (int y = y0; y < y1; ++y) {
+        T v[L::Q];
+        const size_t r0 = row_of(y), rp2 = row_of(y + 2);
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (L::xi[i][1] > 0.0) {      // upwind rows y-2 (A), y-1 (B), y (new)
+                const T Cn = xadv(I, r0);
+                v[i] = Cn - cf.alpha[1][i] * (Cn - B[i]) + cf.beta[1][i] * (B[i] - A[i]);
+                A[i] = B[i];
+                B[i] = Cn;
+            } else {                                 // upwind rows y (A), y+1 (B), y+2 (new)
+                const T Cn = xadv(I, rp2);
+                v[i] = A[i] - cf.alpha[1][i] * (A[i] - B[i]) + cf.beta[1][i] * (B[i] - Cn);
+                A[i] = B[i];
+                B[i] = Cn;
+            }
+        });
+        collide<L, N, S, T>(v, om);
+        const size_t o = r0 + (size_t)x;
+        const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+        });
+    }
+}
+
+// ---------------------------------------------------------------- initial state
+// SplitMix64 (Steele, Lea, Flood 2014): output k+1 of the stream started at seed.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <class L, int N, int S>
+__global__ __launch_bounds__(kBlock) void k_init_wave(WaveArgs a) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    const uint32_t yz = cell / (uint32_t)a.nx;
+    const uint32_t j = a.wave_axis == 1 ? yz % (uint32_t)a.ny : yz / (uint32_t)a.ny;
+    double rho = 1.0;
+    if (a.rho_noise != 0.0) {
+        const double U = (double)(splitmix64_at(a.seed, cell) >> 11) * 0x1.0p-53;
+        rho = 1.0 + a.rho_noise * (2.0 * U - 1.0);
+    }
+    const double ux = a.u0 * a.sin_tab[j];
+    double v[L::Q];
+    equilibrium_v<L, N, S>(rho, ux, 0.0, 0.0, v);
+    raw *f = static_cast<raw *>(a.f);
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        f[(size_t)i * a.pstride + cell] = C::template enc<false>((typename C::T)v[i], 0u);
+    });
+}
+
+template <class L, int N, int S>
+__global__ __launch_bounds__(kBlock) void k_init_fields(void *fv, uint32_t ps, uint32_t ncell,
+                                                        const double *rho, const double *u) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    double v[L::Q];
+    equilibrium_v<L, N, S>(rho[cell], u[cell], u[ncell + cell], L::D == 3 ? u[2 * (size_t)ncell + cell] : 0.0, v);
+    raw *f = static_cast<raw *>(fv);
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        f[(size_t)i * ps + cell] = C::template enc<false>((typename C::T)v[i], 0u);
+    });
+}
+
+// ---------------------------------------------------------------- codec kernels
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_decode(const void *fv, uint32_t ps, uint32_t ncell, int a,
+                                                   double add, double mul, double *out) {
+    using C = Codec<S>;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    const auto *f = static_cast<const typename C::raw *>(fv);
+    out[cell] = add + mul * C::dec64(f[(size_t)a * ps + cell]);
+}
+
+template <int S, bool SR>
+__global__ __launch_bounds__(kBlock) void k_encode(void *fv, uint32_t ps, uint32_t ncell, int a, double add,
+                                                   double scale, const double *in, uint32_t key) {
+    using C = Codec<S>;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    auto *f = static_cast<typename C::raw *>(fv);
+    const double v = (in[cell] - add) * scale;
+    f[(size_t)a * ps + cell] = C::template enc<SR>((typename C::T)v, SR ? pop_bits(mix32(cell ^ key), a) : 0u);
+}
+
+// rho and u in FP64 from the stored state.
+template <class L, int S>
+__global__ __launch_bounds__(kBlock) void k_moments(const void *fv, uint32_t ps, uint32_t ncell, double *rho,
+                                                    double *u) {
+    using C = Codec<S>;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    const auto *f = static_cast<const typename C::raw *>(fv);
+    double v[L::Q];
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        v[i] = C::dec64(f[(size_t)i * ps + cell]);
+    });
+    const Moments<double> m = project<L, S>(v);
+    const double r = C::dev ? 1.0 + m.d : m.d;
+    rho[cell] = r;
+    u[cell] = m.jx / r;
+    u[ncell + cell] = m.jy / r;
+    if (L::D == 3) u[2 * (size_t)ncell + cell] = m.jz / r;
+}
+
+// Deterministic FP64 reduction, stage 1: fixed grid-stride order per thread, fixed
+// butterfly per wave, fixed order over the waves of the block.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <class L, int S>
+__global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a) {
+    using C = Codec<S>;
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    const auto *f = static_cast<const typename C::raw *>(a.f);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t cell = blockIdx.x * kBlock + threadIdx.x; cell < ncell; cell += gridDim.x * kBlock) {
+        double v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            v[i] = C::dec64(f[(size_t)i * a.pstride + cell]);
+        });
+        const Moments<double> m = project<L, S>(v);
+        const double r = C::dev ? 1.0 + m.d : m.d;
+        const double ux = m.jx / r;
+        const uint32_t yz = cell / (uint32_t)a.nx;
+        const uint32_t j = a.wave_axis == 1 ? yz % (uint32_t)a.ny : yz / (uint32_t)a.ny;
+        acc[0] += ux * a.sin_tab[j];
+        acc[1] += ux * a.cos_tab[j];
+        acc[2] += m.d;
+        acc[3] += m.jx;
+        acc[4] += m.jy;
+        acc[5] += m.jz;
+    }
+    __shared__ double red[kBlock / 64][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        a.partials[(size_t)blockIdx.x * 6 + threadIdx.x] = s;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_finite(const void *fv, uint32_t ps, uint32_t ncell, int Q,
+                                                   int *flag) {
+    using C = Codec<S>;
+    const auto *f = static_cast<const typename C::raw *>(fv);
+    bool bad = false;
+    for (uint32_t cell = blockIdx.x * kBlock + threadIdx.x; cell < ncell; cell += gridDim.x * kBlock)
+        for (int i = 0; i < Q; ++i) bad |= !isfinite((double)C::dec(f[(size_t)i * ps + cell]));
+    if (bad) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------- host launchers
+inline uint32_t blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+
+template <class L, int N, int S, bool SR>
+hipError_t launch_shift_rows(const StepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_shift_rows<L, N, S, SR>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+template <class L, int N, int S, bool SR>
+hipError_t launch_shift_cells(const StepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_shift_cells<L, N, S, SR>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+template <class L, int N, int S, bool SR, class T>
+hipError_t launch_bw2(const StepArgs &a, const BWCoef<T> &cf, hipStream_t s) {
+    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
+    return hipGetLastError();
+}
+template <class L, int N, int S>
+hipError_t launch_init_wave(const WaveArgs &a, hipStream_t s) {
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    hipLaunchKernelGGL((k_init_wave<L, N, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+template <class L, int N, int S>
+hipError_t launch_init_fields(void *f, uint32_t ps, uint32_t ncell, const double *rho, const double *u,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((k_init_fields<L, N, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, rho, u);
+    return hipGetLastError();
+}
+template <int S>
+hipError_t launch_decode(const void *f, uint32_t ps, uint32_t ncell, int a, double add, double mul, double *out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((k_decode<S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, a, add, mul, out);
+    return hipGetLastError();
+}
+template <int S, bool SR>
+hipError_t launch_encode(void *f, uint32_t ps, uint32_t ncell, int a, double add, double scale, const double *in,
+                         uint32_t key, hipStream_t s) {
+    hipLaunchKernelGGL((k_encode<S, SR>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, a, add, scale,
+                       in, key);
+    return hipGetLastError();
+}
+template <class L, int S>
+hipError_t launch_moments(const void *f, uint32_t ps, uint32_t ncell, double *rho, double *u, hipStream_t s) {
+    hipLaunchKernelGGL((k_moments<L, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, rho, u);
+    return hipGetLastError();
+}
+template <class L, int S>
+hipError_t launch_diag(const DiagArgs &a, uint32_t nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_diag<L, S>), dim3(nblocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+template <int S>
+hipError_t launch_finite(const void *f, uint32_t ps, uint32_t ncell, int Q, int *flag, hipStream_t s) {
+    uint32_t nb = blocks_for(ncell);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL((k_finite<S>), dim3(nb), dim3(kBlock), 0, s, f, ps, ncell, Q, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- registration
+template <class L, int N, int S, bool SR>
+KernelSet make_set() {
+    KernelSet k{};
+    k.lattice = L::id;
+    k.order = N;
+    k.storage = S;
+    k.sr = SR ? 1 : 0;
+    if constexpr (L::on_lattice) {
+        k.shift_rows = &launch_shift_rows<L, N, S, SR>;
+        k.shift_cells = &launch_shift_cells<L, N, S, SR>;
+    } else if constexpr (L::D == 2) {
+        if constexpr (S == ST_FP64)
+            k.bw2_f64 = &launch_bw2<L, N, S, SR, double>;
+        else
+            k.bw2_f32 = &launch_bw2<L, N, S, SR, float>;
+    }
+    k.init_wave = &launch_init_wave<L, N, S>;
+    k.init_fields = &launch_init_fields<L, N, S>;
+    k.decode = &launch_decode<S>;
+    k.encode = &launch_encode<S, SR>;
+    k.moments = &launch_moments<L, S>;
+    k.diag = &launch_diag<L, S>;
+    k.finite = &launch_finite<S>;
+    return k;
+}
+
+template <class L, int N>
+void register_order(std::vector<KernelSet> &r) {
+    r.push_back(make_set<L, N, ST_FP64, false>());
+    r.push_back(make_set<L, N, ST_FP32, false>());
+    r.push_back(make_set<L, N, ST_FP32_DEV, false>());
+    r.push_back(make_set<L, N, ST_FP16_DEV, false>());
+    r.push_back(make_set<L, N, ST_FP16_DEV, true>());
+    r.push_back(make_set<L, N, ST_BF16_DEV, false>());
+    r.push_back(make_set<L, N, ST_BF16_DEV, true>());
+}
+
+template <class L>
+void register_lattice() {
+    auto &r = registry();
+    register_order<L, 1>(r);
+    register_order<L, 2>(r);
+    register_order<L, 3>(r);
+    register_order<L, 4>(r);
+}
+
+}  // namespace lbm

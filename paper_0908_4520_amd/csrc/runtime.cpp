@@ -1,0 +1,626 @@
+// runtime.cpp -- host side of the C ABI declared in include/lbm.h: argument validation,
+// device buffers, kernel selection, step loop, readbacks and the decay-rate fit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "lattices.inc"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+struct LatInfo {
+    int id, Q, D, R, degree;
+    bool on_lattice;
+    double scale, xi_max;
+    const int (*c)[3];
+    const double (*xi)[3];
+    const double *w;
+};
+
+template <class L>
+LatInfo info_of() {
+    return LatInfo{L::id, L::Q, L::D, L::R, L::degree, L::on_lattice, L::scale, L::xi_max, L::c, L::xi, L::w};
+}
+
+const LatInfo *lat_info(int id) {
+    static const LatInfo table[] = {info_of<D2Q9>(),     info_of<D2Q37>(), info_of<D3Q39>(),
+                                    info_of<D2Q16_GH>(), info_of<D2Q36_GH>(), info_of<D2Q16_CK>(),
+                                    info_of<D2Q17>(),    info_of<D2Q21>(), info_of<D2Q25_CK>()};
+    for (const auto &t : table)
+        if (t.id == id) return &t;
+    return nullptr;
+}
+
+void ensure_registered() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_D2Q9();
+        register_D2Q37();
+        register_D3Q39();
+        register_D2Q16_GH();
+        register_D2Q36_GH();
+        register_D2Q16_CK();
+        register_D2Q17();
+        register_D2Q21();
+        register_D2Q25_CK();
+    });
+}
+
+const KernelSet *find_kernels(int lat, int N, int storage, int sr) {
+    ensure_registered();
+    for (const auto &k : registry())
+        if (k.lattice == lat && k.order == N && k.storage == storage && k.sr == sr) return &k;
+    return nullptr;
+}
+
+int elem_size(lbm_storage s) {
+    switch (s) {
+        case LBM_FP64: return 8;
+        case LBM_FP32:
+        case LBM_FP32_DEV: return 4;
+        default: return 2;
+    }
+}
+bool is_dev(lbm_storage s) { return s == LBM_FP32_DEV || s == LBM_FP16_DEV || s == LBM_BF16_DEV; }
+bool is_scaled(lbm_storage s) { return s == LBM_FP16_DEV; }
+
+uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Step-kernel tile choices: chunks of 256 cells per block (shift) or strip rows (Beam-Warming).
+const int kShiftTiles[] = {1, 2, 4, 8};
+const int kBWTiles[] = {8, 16, 32, 4, 64};
+
+}  // namespace
+
+struct lbm_sim {
+    const LatInfo *L = nullptr;
+    int N = 0;
+    double tau = 0, omega = 0;
+    lbm_grid g{};
+    size_t ncell = 0;
+    uint32_t pstride = 0;
+    lbm_opts o{};
+    lbm_move move = LBM_MOVE_AUTO;
+    int esize = 0;
+    hipStream_t stream = nullptr;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t nstep = 0;
+    const KernelSet *ks = nullptr;
+    bool rows_ok = false;       // row-tiled shift kernel is valid for this grid
+    int tile = 0;
+    double *d_tab = nullptr;    // sin then cos table of the current wave axis
+    int tab_axis = -1;
+    double *d_partials = nullptr;
+    double *d_result = nullptr;
+    int *d_flag = nullptr;
+    uint32_t diag_blocks = 0;
+    uint32_t warnings = 0;
+    BWCoef<float> bwf{};
+    BWCoef<double> bwd{};
+};
+
+namespace {
+
+StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index) {
+    StepArgs a{};
+    a.fin = fin;
+    a.fout = fout;
+    a.nx = s->g.nx;
+    a.ny = s->g.ny;
+    a.nz = s->g.nz;
+    a.pstride = s->pstride;
+    a.omega = s->omega;
+    a.sr_key = (uint32_t)splitmix64(s->o.sr_seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(s->nstep + 1)));
+    const uint32_t nx = (uint32_t)s->g.nx;
+    if (s->move == LBM_MOVE_BW2) {
+        const uint32_t H = (uint32_t)kBWTiles[tile_index];
+        a.tile = H;
+        a.per_row = (nx + kBlock - 1) / kBlock;
+        a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
+    } else if (s->rows_ok) {
+        const uint32_t cpt = (uint32_t)kShiftTiles[tile_index];
+        a.tile = cpt;
+        a.per_row = (nx + kBlock * cpt - 1) / (kBlock * cpt);
+        a.nblocks = a.per_row * (uint32_t)s->g.ny * (uint32_t)s->g.nz;
+    } else {
+        a.tile = 1;
+        a.per_row = 1;
+        a.nblocks = (uint32_t)((s->ncell + kBlock - 1) / kBlock);
+    }
+    return a;
+}
+
+hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index) {
+    const StepArgs a = step_args(s, fin, fout, tile_index);
+    if (s->move == LBM_MOVE_BW2)
+        return s->o.storage == LBM_FP64 ? s->ks->bw2_f64(a, s->bwd, s->stream) : s->ks->bw2_f32(a, s->bwf, s->stream);
+    return s->rows_ok ? s->ks->shift_rows(a, s->stream) : s->ks->shift_cells(a, s->stream);
+}
+
+int tile_count(const lbm_sim *s) {
+    if (s->move == LBM_MOVE_BW2) return (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
+    if (s->rows_ok) return (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]);
+    return 1;
+}
+
+lbm_status ensure_tables(lbm_sim *s, int axis) {
+    if (s->tab_axis == axis) return LBM_OK;
+    const int nw = axis == 1 ? s->g.ny : s->g.nz;
+    std::vector<double> h(2 * (size_t)nw);
+    for (int j = 0; j < nw; ++j) {
+        const double ph = 2.0 * M_PI * (double)j / (double)nw;
+        h[j] = sin(ph);
+        h[nw + j] = cos(ph);
+    }
+    if (s->d_tab) HIP_TRY(hipFree(s->d_tab));
+    s->d_tab = nullptr;
+    s->tab_axis = -1;
+    HIP_TRY(hipMalloc(&s->d_tab, sizeof(double) * h.size()));
+    HIP_TRY(hipMemcpyAsync(s->d_tab, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->tab_axis = axis;
+    return LBM_OK;
+}
+
+lbm_status check_axis(const lbm_sim *s, int axis) {
+    if (axis == 1) return LBM_OK;
+    if (axis == 2 && s->L->D == 3) return LBM_OK;
+    return fail(LBM_EINVAL, "wave_axis must be 1 (y) or, for 3-D sets, 2 (z); got %d", axis);
+}
+
+// Runs the diagnostic reduction and copies the 6 sums to host.
+lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
+    lbm_status st = ensure_tables(s, axis);
+    if (st != LBM_OK) return st;
+    DiagArgs a{};
+    a.f = s->buf[s->cur];
+    a.nx = s->g.nx;
+    a.ny = s->g.ny;
+    a.nz = s->g.nz;
+    a.pstride = s->pstride;
+    a.wave_axis = axis;
+    const int nw = axis == 1 ? s->g.ny : s->g.nz;
+    a.sin_tab = s->d_tab;
+    a.cos_tab = s->d_tab + nw;
+    a.partials = s->d_partials;
+    HIP_TRY(s->ks->diag(a, s->diag_blocks, s->stream));
+    HIP_TRY(diag_final(s->d_partials, s->diag_blocks, s->d_result, s->stream));
+    HIP_TRY(hipMemcpyAsync(out, s->d_result, 6 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_opts_default(lbm_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->storage = LBM_FP64;
+    o->move = LBM_MOVE_AUTO;
+    o->cfl = 0.5;
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_lattice_info(lbm_lattice lat, int32_t *Q, int32_t *D, int32_t *c, double *xi, double *w) {
+    const LatInfo *L = lat_info((int)lat);
+    if (!L) return fail(LBM_EINVAL, "unknown lattice %d", (int)lat);
+    if (Q) *Q = L->Q;
+    if (D) *D = L->D;
+    for (int a = 0; a < L->Q; ++a) {
+        for (int d = 0; d < 3; ++d) {
+            if (c) c[3 * a + d] = L->c[a][d];
+            if (xi) xi[3 * a + d] = L->xi[a][d];
+        }
+        if (w) w[a] = L->w[a];
+    }
+    return LBM_OK;
+}
+
+double lbm_tau_from_kn(lbm_lattice lat, lbm_move move, double kn, int32_t wavelength_cells, double cfl) {
+    const LatInfo *L = lat_info((int)lat);
+    if (!L || !(kn >= 0.0) || wavelength_cells < 1) return NAN;
+    if (move == LBM_MOVE_AUTO) move = L->on_lattice ? LBM_MOVE_SHIFT : LBM_MOVE_BW2;
+    const double dx = 2.0 * M_PI / (double)wavelength_cells;
+    double dt;
+    if (move == LBM_MOVE_SHIFT) {
+        if (!L->on_lattice) return NAN;
+        dt = dx / L->scale;
+    } else {
+        if (!(cfl > 0.0 && cfl <= 1.0)) return NAN;
+        dt = cfl * dx / L->xi_max;
+    }
+    return kn / dt + 0.5;
+}
+
+lbm_status lbm_init(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g) {
+    return lbm_init_ex(out, lat, eq_order, tau, g, nullptr);
+}
+
+lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g,
+                       const lbm_opts *opts) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const LatInfo *L = lat_info((int)lat);
+    if (!L) return fail(LBM_EINVAL, "unknown lattice %d", (int)lat);
+    if (eq_order < 1 || eq_order > 4) return fail(LBM_EINVAL, "eq_order must be 1..4, got %d", eq_order);
+    if (!(tau > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2 (or +inf), got %g", tau);
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(LBM_EINVAL, "grid dimensions must be >= 1");
+    if (L->D == 2 && g.nz != 1) return fail(LBM_EINVAL, "2-D velocity set needs nz = 1, got %d", g.nz);
+    const unsigned long long ncell = (unsigned long long)g.nx * g.ny * g.nz;
+    if (ncell > 0x7fffffffull) return fail(LBM_EINVAL, "grid of %llu cells exceeds 2^31 - 1", ncell);
+    lbm_opts o;
+    lbm_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.storage < LBM_FP64 || o.storage > LBM_BF16_DEV) return fail(LBM_EINVAL, "unknown storage %d", (int)o.storage);
+    lbm_move move = o.move;
+    if (move == LBM_MOVE_AUTO) move = L->on_lattice ? LBM_MOVE_SHIFT : LBM_MOVE_BW2;
+    if (move == LBM_MOVE_SHIFT && !L->on_lattice)
+        return fail(LBM_EINVAL, "exact shift needs an on-lattice velocity set");
+    if (move == LBM_MOVE_BW2) {
+        if (L->on_lattice) return fail(LBM_EINVAL, "upwind advection is provided for the off-lattice sets");
+        if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1], got %g", o.cfl);
+    }
+    if (move != LBM_MOVE_SHIFT && move != LBM_MOVE_BW2) return fail(LBM_EINVAL, "unknown move %d", (int)move);
+    if (o.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+    const int sr = (o.stochastic_round && (o.storage == LBM_FP16_DEV || o.storage == LBM_BF16_DEV)) ? 1 : 0;
+    const KernelSet *ks = find_kernels((int)lat, eq_order, (int)o.storage, sr);
+    if (!ks) return fail(LBM_EINVAL, "no kernels for lattice %d order %d storage %d", (int)lat, eq_order, (int)o.storage);
+
+    lbm_sim *s = new lbm_sim();
+    s->L = L;
+    s->N = eq_order;
+    s->tau = tau;
+    s->omega = isinf(tau) ? 0.0 : 1.0 / tau;
+    s->g = g;
+    s->ncell = (size_t)ncell;
+    s->pstride = (uint32_t)((ncell + 63) / 64 * 64);
+    s->o = o;
+    s->move = move;
+    s->esize = elem_size(o.storage);
+    s->stream = (hipStream_t)o.hip_stream;
+    s->ks = ks;
+    s->rows_ok = move == LBM_MOVE_SHIFT && g.nx >= 256 && g.nx >= L->R && g.ny >= L->R && (L->D == 2 || g.nz >= L->R);
+    s->tile = (o.tile > 0 && o.tile < tile_count(s)) ? o.tile : 0;
+    if (L->degree < 2 * eq_order) s->warnings |= LBM_WARN_QUADRATURE;
+    if (move == LBM_MOVE_BW2) {
+        const double lam = o.cfl / L->xi_max;
+        for (int a = 0; a < L->Q; ++a)
+            for (int d = 0; d < 2; ++d) {
+                const double A = fabs(L->xi[a][d] * lam);
+                const double b = 0.5 * A * (1.0 - A);
+                s->bwd.alpha[d][a] = A + b;
+                s->bwd.beta[d][a] = b;
+                s->bwf.alpha[d][a] = (float)(A + b);
+                s->bwf.beta[d][a] = (float)b;
+            }
+    }
+    s->diag_blocks = (uint32_t)std::min<size_t>((s->ncell + kBlock - 1) / kBlock, 2048);
+    const size_t bytes = (size_t)L->Q * s->pstride * (size_t)s->esize;
+    hipError_t e = hipMalloc(&s->buf[0], bytes);
+    if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
+    if (e == hipSuccess) e = hipMalloc(&s->d_partials, sizeof(double) * 6 * s->diag_blocks);
+    if (e == hipSuccess) e = hipMalloc(&s->d_result, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMalloc(&s->d_flag, sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(s->buf[0], 0, bytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->buf[1], 0, bytes, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        lbm_status st = fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                             "allocating %zu bytes of populations: %s", 2 * bytes, hipGetErrorString(e));
+        lbm_free(s);
+        (void)hipGetLastError();
+        return st;
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+void lbm_free(lbm_sim *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (void *p : {s->buf[0], s->buf[1], (void *)s->d_tab, (void *)s->d_partials, (void *)s->d_result,
+                    (void *)s->d_flag})
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+uint32_t lbm_warnings(const lbm_sim *s) { return s ? s->warnings : 0u; }
+
+int64_t lbm_step_count(const lbm_sim *s) { return s ? s->nstep : -1; }
+
+lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, int64_t *bytes_per_step) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (ncell) *ncell = (int64_t)s->ncell;
+    if (Q) *Q = s->L->Q;
+    if (D) *D = s->L->D;
+    if (bytes_per_step) *bytes_per_step = 2ll * s->L->Q * (int64_t)s->ncell * s->esize;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double rho_noise, uint64_t seed) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    lbm_status st = check_axis(s, wave_axis);
+    if (st != LBM_OK) return st;
+    if (!isfinite(u0) || !isfinite(rho_noise) || fabs(rho_noise) >= 1.0)
+        return fail(LBM_EINVAL, "u0 and rho_noise must be finite, |rho_noise| < 1");
+    st = ensure_tables(s, wave_axis);
+    if (st != LBM_OK) return st;
+    WaveArgs a{};
+    a.f = s->buf[0];
+    a.nx = s->g.nx;
+    a.ny = s->g.ny;
+    a.nz = s->g.nz;
+    a.pstride = s->pstride;
+    a.wave_axis = wave_axis;
+    a.u0 = u0;
+    a.rho_noise = rho_noise;
+    a.seed = seed;
+    a.sin_tab = s->d_tab;
+    HIP_TRY(s->ks->init_wave(a, s->stream));
+    s->cur = 0;
+    s->nstep = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_sim *s, const double *rho, const double *u) {
+    if (!s || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = s->ncell, D = (size_t)s->L->D;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * n * (1 + D)));
+    hipError_t e = hipMemcpyAsync(d, rho, sizeof(double) * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, u, sizeof(double) * n * D, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = s->ks->init_fields(s->buf[0], s->pstride, (uint32_t)n, d, d + n, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    HIP_TRY(e);
+    s->cur = 0;
+    s->nstep = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_sim *s, int64_t n) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    for (int64_t k = 0; k < n; ++k) {
+        HIP_TRY(launch_step(s, s->buf[s->cur], s->buf[s->cur ^ 1], s->tile));
+        s->cur ^= 1;
+        s->nstep += 1;
+        if (s->o.check_every > 0 && s->nstep % s->o.check_every == 0) {
+            HIP_TRY(fill_zero(s->d_flag, 1, s->stream));
+            HIP_TRY(s->ks->finite(s->buf[s->cur], s->pstride, (uint32_t)s->ncell, s->L->Q, s->d_flag, s->stream));
+            int flag = 0;
+            HIP_TRY(hipMemcpyAsync(&flag, s->d_flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            if (flag) return fail(LBM_ENONFINITE, "non-finite population after step %lld", (long long)s->nstep);
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim *s, double *rho, double *u) {
+    if (!s || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = s->ncell, D = (size_t)s->L->D;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * n * (1 + D)));
+    hipError_t e = s->ks->moments(s->buf[s->cur], s->pstride, (uint32_t)n, d, d + n, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rho, d, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(u, d + n, sizeof(double) * n * D, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    HIP_TRY(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_shear_amplitude(lbm_sim *s, int32_t wave_axis, double *a_sin, double *a_cos) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    lbm_status st = check_axis(s, wave_axis);
+    if (st != LBM_OK) return st;
+    double r[6];
+    st = run_diag(s, wave_axis, r);
+    if (st != LBM_OK) return st;
+    const double scale = 2.0 / (double)s->ncell;
+    if (a_sin) *a_sin = scale * r[0];
+    if (a_cos) *a_cos = scale * r[1];
+    return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_sim *s, double *mass, double *mom) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    double r[6];
+    lbm_status st = run_diag(s, 1, r);
+    if (st != LBM_OK) return st;
+    if (mass) *mass = (is_dev(s->o.storage) ? (double)s->ncell : 0.0) + r[2];
+    if (mom)
+        for (int d = 0; d < s->L->D; ++d) mom[d] = r[3 + d];
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_sim *s, double *f) {
+    if (!s || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = s->ncell;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * n));
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < s->L->Q && e == hipSuccess; ++a) {
+        const double add = is_dev(s->o.storage) ? s->L->w[a] : 0.0;
+        const double mul = is_scaled(s->o.storage) ? s->L->w[a] : 1.0;
+        e = s->ks->decode(s->buf[s->cur], s->pstride, (uint32_t)n, a, add, mul, d, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(f + (size_t)a * n, d, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    (void)hipFree(d);
+    HIP_TRY(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_sim *s, const double *f) {
+    if (!s || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = s->ncell;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * n));
+    hipError_t e = hipSuccess;
+    const uint32_t key = (uint32_t)splitmix64(s->o.sr_seed ^ 0xC0FFEEull);
+    for (int a = 0; a < s->L->Q && e == hipSuccess; ++a) {
+        const double add = is_dev(s->o.storage) ? s->L->w[a] : 0.0;
+        const double scale = is_scaled(s->o.storage) ? 1.0 / s->L->w[a] : 1.0;
+        e = hipMemcpyAsync(d, f + (size_t)a * n, sizeof(double) * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = s->ks->encode(s->buf[s->cur], s->pstride, (uint32_t)n, a, add, scale, d, key, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    (void)hipFree(d);
+    HIP_TRY(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step_count(lbm_sim *s, int64_t n) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "step count must be >= 0");
+    s->nstep = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(const lbm_sim *s, int64_t *bytes) {
+    if (!s || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    *bytes = (int64_t)s->L->Q * (int64_t)s->pstride * s->esize;
+    return LBM_OK;
+}
+
+lbm_status lbm_save_state(lbm_sim *s, void *host, int64_t bytes) {
+    int64_t need = 0;
+    lbm_status st = lbm_state_bytes(s, &need);
+    if (st != LBM_OK) return st;
+    if (!host || bytes != need) return fail(LBM_EINVAL, "state needs exactly %lld bytes", (long long)need);
+    HIP_TRY(hipMemcpyAsync(host, s->buf[s->cur], (size_t)need, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes) {
+    int64_t need = 0;
+    lbm_status st = lbm_state_bytes(s, &need);
+    if (st != LBM_OK) return st;
+    if (!host || bytes != need) return fail(LBM_EINVAL, "state needs exactly %lld bytes", (long long)need);
+    HIP_TRY(hipMemcpyAsync(s->buf[s->cur], host, (size_t)need, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_fit_decay(const double *amp, const int64_t *steps, int64_t count, int64_t n_first, int64_t n_last,
+                         double *gamma) {
+    if (!amp || !steps || !gamma || count < 0) return fail(LBM_EINVAL, "NULL argument or negative count");
+    double st = 0, sy = 0;
+    int64_t m = 0;
+    for (int64_t k = 0; k < count; ++k)
+        if (steps[k] >= n_first && steps[k] <= n_last) {
+            if (!(amp[k] != 0.0) || !isfinite(amp[k])) return fail(LBM_EINVAL, "amplitude %lld is zero or non-finite", (long long)k);
+            st += (double)steps[k];
+            sy += -log(fabs(amp[k]));
+            ++m;
+        }
+    if (m < 2) return fail(LBM_EINVAL, "fewer than two points in the fit window");
+    const double tm = st / (double)m, ym = sy / (double)m;
+    double sxy = 0, sxx = 0;
+    for (int64_t k = 0; k < count; ++k)
+        if (steps[k] >= n_first && steps[k] <= n_last) {
+            const double dt = (double)steps[k] - tm;
+            sxy += dt * (-log(fabs(amp[k])) - ym);
+            sxx += dt * dt;
+        }
+    if (!(sxx > 0.0)) return fail(LBM_EINVAL, "fit window has a single distinct step");
+    *gamma = sxy / sxx;
+    return LBM_OK;
+}
+
+int32_t lbm_tile_count(const lbm_sim *s) { return s ? tile_count(s) : 0; }
+
+lbm_status lbm_set_tile(lbm_sim *s, int32_t tile) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (tile < 0 || tile >= tile_count(s)) return fail(LBM_EINVAL, "tile %d out of range [0, %d)", tile, tile_count(s));
+    s->tile = tile;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile, double *best_ms) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    const size_t bytes = (size_t)s->L->Q * s->pstride * (size_t)s->esize;
+    void *scratch[2] = {nullptr, nullptr};
+    HIP_TRY(hipMalloc(&scratch[0], bytes));
+    hipError_t e = hipMalloc(&scratch[1], bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(scratch[0], s->buf[s->cur], bytes, hipMemcpyDeviceToDevice, s->stream);
+    int best = s->tile;
+    float best_t = 1e30f;
+    const int64_t saved_step = s->nstep;
+    for (int t = 0; t < tile_count(s) && e == hipSuccess; ++t) {
+        int c = 0;
+        e = launch_step(s, scratch[c], scratch[c ^ 1], t);   // warm-up
+        c ^= 1;
+        if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+        for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k) {
+            e = launch_step(s, scratch[c], scratch[c ^ 1], t);
+            c ^= 1;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_t) {
+            best_t = ms;
+            best = t;
+        }
+    }
+    s->nstep = saved_step;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch[0]);
+    if (scratch[1]) (void)hipFree(scratch[1]);
+    HIP_TRY(e);
+    s->tile = best;
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = (double)best_t / steps_per_trial;
+    return LBM_OK;
+}
+
+}  // extern "C"

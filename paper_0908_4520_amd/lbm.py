@@ -1,0 +1,247 @@
+"""ctypes binding of liblbm.so (include/lbm.h): the same names, argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module converts numpy
+arrays and Python numbers to C arguments and turns error codes into exceptions.  There is
+no fallback: if the library is missing or fails to load, importing raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "liblbm.so"
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LATTICES = {"D2Q9": 1, "D2Q37": 2, "D3Q39": 3, "D2Q16-GH": 4, "D2Q36-GH": 5, "D2Q16-CK": 6,
+            "D2Q17": 7, "D2Q21": 8, "D2Q25-CK": 9}
+STORAGES = {"fp64": 0, "fp32": 1, "fp32_dev": 2, "fp16_dev": 3, "bf16_dev": 4}
+MOVES = {"auto": 0, "shift": 1, "bw2": 2}
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2}
+LBM_WARN_QUADRATURE = 1
+
+
+class lbm_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class lbm_opts(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int), ("move", ctypes.c_int), ("cfl", ctypes.c_double),
+                ("stochastic_round", ctypes.c_int32), ("sr_seed", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p), ("check_every", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_SIM = ctypes.c_void_p
+
+# name: (restype, argtypes) -- every symbol declared in include/lbm.h
+SIGNATURES = {
+    "lbm_opts_default": (None, [ctypes.POINTER(lbm_opts)]),
+    "lbm_lattice_info": (ctypes.c_int, [ctypes.c_int, _I32, _I32, _I32, _D, _D]),
+    "lbm_tau_from_kn": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int32, ctypes.c_double]),
+    "lbm_init": (ctypes.c_int, [ctypes.POINTER(_SIM), ctypes.c_int, ctypes.c_int32, ctypes.c_double, lbm_grid]),
+    "lbm_init_ex": (ctypes.c_int, [ctypes.POINTER(_SIM), ctypes.c_int, ctypes.c_int32, ctypes.c_double, lbm_grid,
+                                   ctypes.POINTER(lbm_opts)]),
+    "lbm_free": (None, [_SIM]),
+    "lbm_warnings": (ctypes.c_uint32, [_SIM]),
+    "lbm_set_shear_wave": (ctypes.c_int, [_SIM, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64]),
+    "lbm_init_equilibrium": (ctypes.c_int, [_SIM, _D, _D]),
+    "lbm_step": (ctypes.c_int, [_SIM, ctypes.c_int64]),
+    "lbm_step_count": (ctypes.c_int64, [_SIM]),
+    "lbm_moments": (ctypes.c_int, [_SIM, _D, _D]),
+    "lbm_shear_amplitude": (ctypes.c_int, [_SIM, ctypes.c_int32, _D, _D]),
+    "lbm_totals": (ctypes.c_int, [_SIM, _D, _D]),
+    "lbm_get_populations": (ctypes.c_int, [_SIM, _D]),
+    "lbm_set_populations": (ctypes.c_int, [_SIM, _D]),
+    "lbm_set_step_count": (ctypes.c_int, [_SIM, ctypes.c_int64]),
+    "lbm_state_bytes": (ctypes.c_int, [_SIM, _I64]),
+    "lbm_save_state": (ctypes.c_int, [_SIM, ctypes.c_void_p, ctypes.c_int64]),
+    "lbm_load_state": (ctypes.c_int, [_SIM, ctypes.c_void_p, ctypes.c_int64]),
+    "lbm_fit_decay": (ctypes.c_int, [_D, _I64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _D]),
+    "lbm_tile_count": (ctypes.c_int32, [_SIM]),
+    "lbm_set_tile": (ctypes.c_int, [_SIM, ctypes.c_int32]),
+    "lbm_autotune": (ctypes.c_int, [_SIM, ctypes.c_int32, _I32, _D]),
+    "lbm_sizes": (ctypes.c_int, [_SIM, _I64, _I32, _I32, _I64]),
+    "lbm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not _LIB_PATH.exists():
+        raise ImportError(f"{_LIB_PATH} is not built; run paper_0908_4520_amd.build.build()")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code: int):
+    if code != LBM_OK:
+        raise LbmError(code, _lib.lbm_last_error().decode(errors="replace"))
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+# ------------------------------------------------------------------ C names
+def lbm_opts_default() -> lbm_opts:
+    o = lbm_opts()
+    _lib.lbm_opts_default(ctypes.byref(o))
+    return o
+
+
+def lbm_lattice_info(lattice: str):
+    """(c[Q,D] int, xi[Q,D], w[Q]) in the library's population order."""
+    Q, D = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.lbm_lattice_info(LATTICES[lattice], ctypes.byref(Q), ctypes.byref(D), None, None, None))
+    c = np.zeros(3 * Q.value, np.int32)
+    xi = np.zeros(3 * Q.value)
+    w = np.zeros(Q.value)
+    _check(_lib.lbm_lattice_info(LATTICES[lattice], None, None, c.ctypes.data_as(_I32), _dp(xi), _dp(w)))
+    return c.reshape(-1, 3)[:, : D.value].copy(), xi.reshape(-1, 3)[:, : D.value].copy(), w
+
+
+def lbm_tau_from_kn(lattice: str, kn: float, wavelength_cells: int, move: str = "auto", cfl: float = 0.5) -> float:
+    t = _lib.lbm_tau_from_kn(LATTICES[lattice], MOVES[move], kn, wavelength_cells, cfl)
+    if math.isnan(t):
+        raise ValueError("invalid arguments to lbm_tau_from_kn")
+    return t
+
+
+def lbm_fit_decay(amp, steps, n_first: int, n_last: int) -> float:
+    amp = np.ascontiguousarray(amp, dtype=np.float64)
+    st = np.ascontiguousarray(steps, dtype=np.int64)
+    g = ctypes.c_double()
+    _check(_lib.lbm_fit_decay(_dp(amp), st.ctypes.data_as(_I64), len(amp), n_first, n_last, ctypes.byref(g)))
+    return g.value
+
+
+class Sim:
+    """Owner of one lbm_sim*; methods are the C calls of the same name without the prefix."""
+
+    def __init__(self, lattice: str, eq_order: int, tau: float, grid, storage: str = "fp64",
+                 move: str = "auto", cfl: float = 0.5, stochastic_round: bool = False, sr_seed: int = 0,
+                 stream=None, check_every: int = 0, tile: int = 0):
+        o = lbm_opts_default()
+        o.storage = STORAGES[storage]
+        o.move = MOVES[move]
+        o.cfl = cfl
+        o.stochastic_round = 1 if stochastic_round else 0
+        o.sr_seed = sr_seed
+        o.hip_stream = stream
+        o.check_every = check_every
+        o.tile = tile
+        g = lbm_grid(*[int(v) for v in grid])
+        h = _SIM()
+        _check(_lib.lbm_init_ex(ctypes.byref(h), LATTICES[lattice], eq_order, float(tau), g, ctypes.byref(o)))
+        self._h = h
+        self.lattice, self.eq_order, self.tau, self.grid, self.storage = lattice, eq_order, tau, tuple(grid), storage
+        n, Q, D, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_lib.lbm_sizes(h, ctypes.byref(n), ctypes.byref(Q), ctypes.byref(D), ctypes.byref(b)))
+        self.ncell, self.Q, self.D, self.bytes_per_step = n.value, Q.value, D.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbm_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def warnings(self) -> int:
+        return _lib.lbm_warnings(self._h)
+
+    def set_shear_wave(self, u0: float, wave_axis: int, rho_noise: float = 0.0, seed: int = 1):
+        _check(_lib.lbm_set_shear_wave(self._h, u0, wave_axis, rho_noise, seed))
+
+    def init_equilibrium(self, rho: np.ndarray, u: np.ndarray):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.ncell)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.D * self.ncell)
+        _check(_lib.lbm_init_equilibrium(self._h, _dp(rho), _dp(u)))
+
+    def step(self, n: int = 1):
+        _check(_lib.lbm_step(self._h, n))
+
+    def step_count(self) -> int:
+        return _lib.lbm_step_count(self._h)
+
+    def set_step_count(self, n: int):
+        _check(_lib.lbm_set_step_count(self._h, n))
+
+    def moments(self):
+        rho = np.empty(self.ncell)
+        u = np.empty((self.D, self.ncell))
+        _check(_lib.lbm_moments(self._h, _dp(rho), _dp(u)))
+        return rho, u
+
+    def shear_amplitude(self, wave_axis: int):
+        s, c = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.lbm_shear_amplitude(self._h, wave_axis, ctypes.byref(s), ctypes.byref(c)))
+        return s.value, c.value
+
+    def totals(self):
+        m = ctypes.c_double()
+        p = np.zeros(3)
+        _check(_lib.lbm_totals(self._h, ctypes.byref(m), _dp(p)))
+        return m.value, p[: self.D].copy()
+
+    def get_populations(self) -> np.ndarray:
+        f = np.empty((self.Q, self.ncell))
+        _check(_lib.lbm_get_populations(self._h, _dp(f)))
+        return f
+
+    def set_populations(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.Q, self.ncell)
+        _check(_lib.lbm_set_populations(self._h, _dp(f)))
+
+    def save_state(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        _check(_lib.lbm_state_bytes(self._h, ctypes.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        _check(_lib.lbm_save_state(self._h, buf.ctypes.data, n.value))
+        return buf
+
+    def load_state(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(_lib.lbm_load_state(self._h, buf.ctypes.data, buf.size))
+
+    def tile_count(self) -> int:
+        return _lib.lbm_tile_count(self._h)
+
+    def set_tile(self, t: int):
+        _check(_lib.lbm_set_tile(self._h, t))
+
+    def autotune(self, steps_per_trial: int = 5):
+        t, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.lbm_autotune(self._h, steps_per_trial, ctypes.byref(t), ctypes.byref(ms)))
+        return t.value, ms.value

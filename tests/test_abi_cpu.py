@@ -1,0 +1,132 @@
+"""CPU-side checks of the C ABI: every declared symbol is exported, host-only entry points
+behave, invalid arguments are rejected before any device work, and the compiled velocity
+tables agree with the oracle's independent derivation.  No kernel is launched here."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_0908_4520_amd import lbm as m
+    return m
+
+
+def test_every_declared_symbol_is_exported_and_bound(lbm):
+    names = _declared_functions()
+    assert len(names) >= 25
+    lib = lbm.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in lbm.SIGNATURES, f"{n} missing from the Python binding"
+    assert set(lbm.SIGNATURES) == set(names)
+
+
+def test_struct_layouts_match_header(lbm):
+    assert ctypes.sizeof(lbm.lbm_grid) == 12
+    # lbm_opts: int, int, double, int32, uint64, void*, int32, int32 with natural alignment
+    assert ctypes.sizeof(lbm.lbm_opts) == 48
+    o = lbm.lbm_opts_default()
+    assert o.storage == 0 and o.move == 0 and o.cfl == 0.5 and o.hip_stream is None
+
+
+def test_tau_from_kn(lbm):
+    from oracle import bgk as ob
+    from oracle import lattices as OL
+    for name in ("D2Q9", "D2Q37", "D3Q39", "D2Q21"):
+        for kn in (0.01, 0.1, 1.0):
+            assert lbm.lbm_tau_from_kn(name, kn, 4096) == pytest.approx(
+                ob.tau_from_kn(OL.get(name), kn, 4096), rel=1e-14)
+    for name in ("D2Q16-GH", "D2Q36-GH"):
+        assert lbm.lbm_tau_from_kn(name, 1.0, 2048, cfl=0.5) == pytest.approx(
+            ob.tau_from_kn(OL.get(name), 1.0, 2048, 0.5), rel=1e-14)
+    # config 1: Kn = 0.1 on 64 cells, D2Q9
+    assert lbm.lbm_tau_from_kn("D2Q9", 0.1, 64) == pytest.approx(2.2642524653497, rel=1e-12)
+    with pytest.raises(ValueError):
+        lbm.lbm_tau_from_kn("D2Q16-GH", 1.0, 64, move="shift")
+    with pytest.raises(ValueError):
+        lbm.lbm_tau_from_kn("D2Q9", -1.0, 64)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q37", "D3Q39", "D2Q16-GH", "D2Q36-GH", "D2Q16-CK", "D2Q17",
+                                  "D2Q21", "D2Q25-CK"])
+def test_compiled_tables_agree_with_oracle(lbm, name):
+    from oracle import lattices as OL
+    c, xi, w = lbm.lbm_lattice_info(name)
+    vs = OL.get(name)
+    p = np.array([int(np.argmin(np.abs(vs.xi - x).sum(axis=1))) for x in xi])
+    assert sorted(p.tolist()) == list(range(vs.Q))
+    # the oracle evaluates some closed forms in double arithmetic: allow a few ulps
+    np.testing.assert_allclose(xi, vs.xi[p], rtol=4e-16, atol=0)
+    np.testing.assert_allclose(w, vs.w[p], rtol=4e-15, atol=0)
+    if vs.on_lattice:
+        np.testing.assert_array_equal(c, vs.c[p])
+
+
+def test_generated_tables_are_current():
+    gen = os.path.join(ROOT, "paper_0908_4520_amd", "csrc", "gen_lattices.py")
+    res = subprocess.run([sys.executable, gen, "--check"], capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, "lattices.inc differs from gen_lattices.py output: " + res.stderr
+
+
+BAD_INIT = [
+    ("D2Q9", 0, 1.0, (4, 4, 1), {}, "eq_order"),
+    ("D2Q9", 5, 1.0, (4, 4, 1), {}, "eq_order"),
+    ("D2Q9", 2, 0.5, (4, 4, 1), {}, "tau"),
+    ("D2Q9", 2, float("nan"), (4, 4, 1), {}, "tau"),
+    ("D2Q9", 2, 1.0, (0, 4, 1), {}, "grid"),
+    ("D2Q9", 2, 1.0, (4, 4, 2), {}, "nz = 1"),
+    ("D2Q16-GH", 2, 1.0, (4, 4, 1), {"move": "shift"}, "on-lattice"),
+    ("D2Q9", 2, 1.0, (4, 4, 1), {"move": "bw2"}, "off-lattice"),
+    ("D2Q16-GH", 2, 1.0, (4, 4, 1), {"cfl": 1.5}, "cfl"),
+    ("D2Q16-GH", 2, 1.0, (4, 4, 1), {"cfl": 0.0}, "cfl"),
+    ("D3Q39", 2, 1.0, (2048, 2048, 1024), {}, "2^31"),
+    ("D2Q9", 2, 1.0, (4, 4, 1), {"check_every": -1}, "check_every"),
+]
+
+
+@pytest.mark.parametrize("lat,N,tau,grid,kw,msg", BAD_INIT)
+def test_invalid_arguments_rejected_without_device(lbm, lat, N, tau, grid, kw, msg):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Sim(lat, N, tau, grid, **kw)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert msg in str(e.value)
+
+
+def test_fit_decay_host(lbm):
+    steps = np.arange(0, 1000, 10)
+    amp = 1e-3 * np.exp(-2.5e-3 * steps) * (1 + 1e-9 * np.sin(steps))
+    g = lbm.lbm_fit_decay(amp, steps, 100, 900)
+    from oracle import bgk as ob
+    assert g == pytest.approx(ob.decay_rate(amp, steps, 100, 900), rel=1e-12)
+    assert g == pytest.approx(2.5e-3, rel=1e-6)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_fit_decay(amp, steps, 5000, 6000)
+
+
+def test_unknown_lattice_info(lbm):
+    assert lbm.lib().lbm_lattice_info(42, None, None, None, None, None) == lbm.LBM_EINVAL
+    assert b"unknown lattice" in lbm.lib().lbm_last_error()
+
+
+def test_collisionless_tau_accepted_by_validation(lbm):
+    """tau = inf passes validation (it fails later only for lack of a device here)."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Sim("D2Q9", 2, math.inf, (4, 4, 1))
+    assert e.value.code in (lbm.LBM_EDEVICE, lbm.LBM_ENOMEM) or "device" in str(e.value)

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (populations |f_gpu - f_oracle| / |f_oracle|, amplitudes |dA| / A0):
+  * FP64 storage: 1e-12 (FMA contraction and summation order differ from the oracle);
+  * FP32 storages: 1e-5;
+  * 16-bit deviation storages: every step rounds each stored deviation g_b once, with unit
+    roundoff u = 2^-8 (BF16) or 2^-11 (FP16, stored as g/w).  A rounding of size
+    E_b = u max|g_b| moves population b directly and, through rho and j, the equilibrium of
+    every population a by at most omega w_a (1 + |xi_a|) sum_b E_b (1 + |xi_b|).  After n steps
+    (n + 1 roundings) the bound is (n + 1) times that, plus FP32 collision error; asserted
+    with a factor 2 margin.
+  * FP64 initial states: the equilibrium polynomial is evaluated in a different order (and
+    with FMA) on the device, so a few ulps: 2e-15.
+Collisionless runs (tau = inf) must reproduce the shift bit for bit in every storage.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import need_gpu, perm, rel_err, say
+from oracle import bgk as ob
+from oracle import lattices as OL
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(lattice, N, tau, grid, storage="fp64", move="auto", u0=1e-3, axis=1, noise=0.0, seed=1, tile=0):
+    lbm = need_gpu()
+    s = lbm.Sim(lattice, N, tau, grid, storage=storage, move=move, tile=tile)
+    s.set_shear_wave(u0, axis, rho_noise=noise, seed=seed)
+    r = ob.BGK(lattice, N, tau, grid, None if move == "auto" else move)
+    r.set_shear_wave(u0, axis, rho_noise=noise, seed=seed)
+    return s, r
+
+
+def test_library_loads_and_reports_sizes():
+    lbm = need_gpu()
+    with lbm.Sim("D2Q37", 4, 3.0, (300, 17, 1), storage="fp32_dev") as s:
+        assert (s.ncell, s.Q, s.D) == (300 * 17, 37, 2)
+        assert s.bytes_per_step == 2 * 37 * 300 * 17 * 4
+        assert s.tile_count() == 4
+
+
+def test_config1_d2q9_fp64_2000_steps():
+    """D2Q9, N = 2, FP64, 4 x 64, Kn = 0.1 (tau = 2.2642...), 2000 steps."""
+    lbm = need_gpu()
+    tau = lbm.lbm_tau_from_kn("D2Q9", 0.1, 64)
+    assert tau == pytest.approx(ob.tau_from_kn(OL.get("D2Q9"), 0.1, 64), rel=1e-15)
+    s, r = _pair("D2Q9", 2, tau, (4, 64, 1))
+    p = perm("D2Q9")
+    A0 = 1e-3
+    for n in range(0, 2001, 250):
+        s.step(n - s.step_count())
+        r.step(n - r.nstep)
+        a_gpu = s.shear_amplitude(1)
+        a_ref = r.shear_amplitude(1)
+        assert abs(a_gpu[0] - a_ref[0]) <= 1e-12 * A0, (n, a_gpu, a_ref)
+        assert abs(a_gpu[1] - a_ref[1]) <= 1e-12 * A0
+    err = rel_err(s.get_populations(), r.f[p])
+    say(f"config1 max rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+SHIFT_CASES = [
+    ("D2Q9", (300, 13, 1)), ("D2Q9", (7, 5, 1)), ("D2Q9", (1, 2, 1)),
+    ("D2Q37", (300, 11, 1)), ("D2Q37", (5, 4, 1)), ("D2Q37", (2, 1, 1)), ("D2Q37", (520, 3, 1)),
+    ("D3Q39", (260, 5, 4)), ("D3Q39", (3, 4, 5)), ("D3Q39", (1, 1, 7)),
+    ("D2Q21", (257, 6, 1)), ("D2Q17", (9, 8, 1)), ("D2Q16-CK", (270, 9, 1)), ("D2Q25-CK", (300, 8, 1)),
+    ("D2Q25-CK", (6, 5, 1)),
+]
+
+
+@pytest.mark.parametrize("lattice,grid", SHIFT_CASES)
+@pytest.mark.parametrize("storage", ["fp64", "fp32_dev"])
+def test_shift_step_small_grids(lattice, grid, storage):
+    lbm = need_gpu()
+    vs = OL.get(lattice)
+    axis = 2 if vs.D == 3 else 1
+    N = 4 if lattice != "D2Q9" else 2
+    tau = 0.93
+    s, r = _pair(lattice, N, tau, grid, storage, axis=axis, noise=1e-6, seed=3)
+    p = perm(lattice)
+    err0 = rel_err(s.get_populations(), r.f[p])
+    s.step(7)
+    r.step(7)
+    err = rel_err(s.get_populations(), r.f[p])
+    say(f"{lattice} {grid} {storage}: t=0 {err0:.2e}, t=7 {err:.2e}")
+    tol = 1e-12 if storage == "fp64" else 1e-5
+    assert err0 <= tol and err <= tol
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_dev"])
+def test_hermite_orders_d2q37(N, storage):
+    s, r = _pair("D2Q37", N, 1.7, (300, 23, 1), storage, noise=1e-6)
+    s.step(5)
+    r.step(5)
+    err = rel_err(s.get_populations(), r.f[perm("D2Q37")])
+    assert err <= (1e-12 if storage == "fp64" else 1e-5)
+
+
+DVM_CASES = [("D2Q16-GH", (300, 21, 1)), ("D2Q16-GH", (5, 7, 1)), ("D2Q16-GH", (1, 9, 1)),
+             ("D2Q36-GH", (280, 33, 1)), ("D2Q36-GH", (3, 2, 1))]
+
+
+@pytest.mark.parametrize("lattice,grid", DVM_CASES)
+@pytest.mark.parametrize("storage", ["fp64", "fp32_dev"])
+def test_bw2_step_small_grids_all_tiles(lattice, grid, storage):
+    lbm = need_gpu()
+    tau = 37.0
+    r = ob.BGK(lattice, 3, tau, grid, "bw2", cfl=0.5)
+    r.set_shear_wave(1e-3, 1, rho_noise=1e-6, seed=2)
+    r.step(6)
+    p = perm(lattice)
+    with lbm.Sim(lattice, 3, tau, grid, storage=storage, cfl=0.5) as s:
+        for t in range(s.tile_count()):
+            s.set_tile(t)
+            s.set_shear_wave(1e-3, 1, rho_noise=1e-6, seed=2)
+            s.step(6)
+            err = rel_err(s.get_populations(), r.f[p])
+            say(f"{lattice} {grid} {storage} tile {t}: {err:.2e}")
+            assert err <= (1e-12 if storage == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("lattice,grid", [("D2Q9", (300, 10, 1)), ("D2Q37", (300, 9, 1)), ("D3Q39", (270, 4, 8)),
+                                          ("D2Q37", (6, 7, 1))])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_dev", "bf16_dev", "fp16_dev"])
+def test_collisionless_shift_bit_exact(lattice, grid, storage):
+    """tau = inf: after n steps every stored value is the initial value moved by n c_a."""
+    lbm = need_gpu()
+    vs_c, _, _ = lbm.lbm_lattice_info(lattice)
+    D = vs_c.shape[1]
+    with lbm.Sim(lattice, 4, math.inf, grid, storage=storage) as s:
+        s.set_shear_wave(1e-3, 2 if D == 3 else 1, rho_noise=1e-6, seed=9)
+        raw0 = s.save_state()
+        n = 5
+        s.step(n)
+        raw = s.save_state()
+    esize = lbm.STORAGE_BYTES[storage]
+    dt = {8: np.uint64, 4: np.uint32, 2: np.uint16}[esize]
+    ncell = grid[0] * grid[1] * grid[2]
+    Q = vs_c.shape[0]
+    ps = raw0.size // esize // Q
+    a0 = raw0.view(dt).reshape(Q, ps)[:, :ncell].reshape(Q, grid[2], grid[1], grid[0])
+    a1 = raw.view(dt).reshape(Q, ps)[:, :ncell].reshape(Q, grid[2], grid[1], grid[0])
+    for a in range(Q):
+        c = list(vs_c[a]) + [0] * (3 - D)
+        moved = np.roll(a0[a], (n * c[2], n * c[1], n * c[0]), axis=(0, 1, 2))
+        # equal as values (a stored -0.0 may come back as +0.0)
+        if storage in ("fp64", "fp32", "fp32_dev"):
+            fl = {8: np.float64, 4: np.float32}[esize]
+            assert np.array_equal(moved.view(fl), a1[a].view(fl)), a
+        else:
+            neg0 = np.uint16(0x8000)
+            assert np.array_equal(np.where(moved == neg0, 0, moved), np.where(a1[a] == neg0, 0, a1[a])), a
+
+
+def test_initial_state_matches_oracle_fp64():
+    s, r = _pair("D3Q39", 4, 2.0, (260, 3, 5), "fp64", axis=2, noise=1e-6, seed=11)
+    assert rel_err(s.get_populations(), r.f[perm("D3Q39")]) <= 2e-15
+
+
+def test_init_equilibrium_from_fields():
+    lbm = need_gpu()
+    rng = np.random.default_rng(5)
+    grid = (300, 7, 1)
+    n = 300 * 7
+    rho = 1 + 0.01 * rng.uniform(-1, 1, n)
+    u = 0.02 * rng.uniform(-1, 1, (2, n))
+    r = ob.BGK("D2Q37", 3, 1.3, grid)
+    r.set_equilibrium(rho, u)
+    with lbm.Sim("D2Q37", 3, 1.3, grid, storage="fp64") as s:
+        s.init_equilibrium(rho, u)
+        assert rel_err(s.get_populations(), r.f[perm("D2Q37")]) <= 2e-15
+        s.step(3)
+        r.step(3)
+        assert rel_err(s.get_populations(), r.f[perm("D2Q37")]) <= 1e-13
+        rho_g, u_g = s.moments()
+    rho_r, u_r = r.moments()
+    assert np.max(np.abs(rho_g - rho_r)) <= 1e-14
+    assert np.max(np.abs(u_g - u_r)) <= 1e-14
+
+
+@pytest.mark.parametrize("storage,u", [("bf16_dev", 2.0**-8), ("fp16_dev", 2.0**-11)])
+@pytest.mark.parametrize("lattice,grid,axis", [("D2Q37", (300, 12, 1), 1), ("D3Q39", (260, 3, 6), 2)])
+def test_low_precision_storage_parity(storage, u, lattice, grid, axis):
+    tau = 1.4
+    s, r = _pair(lattice, 4, tau, grid, storage, axis=axis)
+    p = perm(lattice)
+    vs = OL.get(lattice)
+    w = vs.w[p][:, None]
+    xin = np.linalg.norm(vs.xi[p], axis=1)[:, None]
+    n = 4
+    s.step(n)
+    r.step(n)
+    E = u * np.max(np.abs(r.f[p] - w), axis=1, keepdims=True)        # rounding scale per population
+    spread = np.sum(E * (1 + xin))
+    bound = 2 * (n + 1) * (E + (1 / tau) * w * (1 + xin) * spread) + 1e-7 * w
+    diff = np.abs(s.get_populations() - r.f[p])
+    say(f"{storage} {lattice}: max diff / bound = {np.max(diff / bound):.3f}")
+    assert np.all(diff <= bound)
+
+
+def test_mass_momentum_conservation_gpu():
+    lbm = need_gpu()
+    with lbm.Sim("D2Q37", 4, 0.8, (300, 40, 1), storage="fp64") as s:
+        s.set_shear_wave(1e-2, 1, rho_noise=1e-3, seed=4)
+        m0, p0 = s.totals()
+        s.step(50)
+        m1, p1 = s.totals()
+    assert abs(m1 - m0) <= 1e-13 * m0
+    assert np.max(np.abs(p1 - p0)) <= 1e-13 * m0
+
+
+@pytest.mark.parametrize("lattice,grid,storage", [("D2Q37", (600, 40, 1), "fp32_dev"),
+                                                  ("D2Q16-GH", (300, 70, 1), "fp32_dev"),
+                                                  ("D3Q39", (300, 6, 9), "bf16_dev")])
+def test_deterministic_and_tile_independent(lattice, grid, storage):
+    lbm = need_gpu()
+    outs = []
+    with lbm.Sim(lattice, 4 if "GH" not in lattice else 3, 2.5, grid, storage=storage,
+                 stochastic_round=storage == "bf16_dev", sr_seed=7) as s:
+        for t in list(range(s.tile_count())) + [0]:
+            s.set_tile(t)
+            s.set_shear_wave(1e-3, 2 if lattice == "D3Q39" else 1, rho_noise=1e-6, seed=1)
+            s.step(9)
+            outs.append(s.save_state())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_checkpoint_resume_bit_exact():
+    lbm = need_gpu()
+    kw = dict(storage="fp16_dev", stochastic_round=True, sr_seed=3)
+    with lbm.Sim("D2Q37", 4, 1.2, (300, 20, 1), **kw) as a, lbm.Sim("D2Q37", 4, 1.2, (300, 20, 1), **kw) as b:
+        a.set_shear_wave(1e-3, 1)
+        b.set_shear_wave(1e-3, 1)
+        a.step(10)
+        snap, n = a.save_state(), a.step_count()
+        a.step(10)
+        b.load_state(snap)
+        b.set_step_count(n)
+        b.step(10)
+        assert np.array_equal(a.save_state(), b.save_state())
+
+
+def test_nonfinite_detection():
+    lbm = need_gpu()
+    with lbm.Sim("D2Q9", 2, 1.0, (300, 4, 1), storage="fp32_dev", check_every=1) as s:
+        s.set_shear_wave(1e-3, 1)
+        f = s.get_populations()
+        f[3, 17] = np.nan
+        s.set_populations(f)
+        with pytest.raises(lbm.LbmError) as e:
+            s.step(2)
+        assert e.value.code == lbm.LBM_ENONFINITE
+
+
+def test_full_size_d2q37_sampled_cells():
+    """4096 x 4096 D2Q37, N = 4, FP32 deviations, density noise 1e-6 (seed 1): after 20
+    steps, sampled cells against the oracle's exact dependence-cone evaluation."""
+    lbm = need_gpu()
+    grid = (4096, 4096, 1)
+    p = perm("D2Q37")
+    for kn in (0.01, 0.1, 1.0):
+        tau = lbm.lbm_tau_from_kn("D2Q37", kn, 4096)
+        with lbm.Sim("D2Q37", 4, tau, grid, storage="fp32_dev") as s:
+            s.set_shear_wave(1e-3, 1, rho_noise=1e-6, seed=1)
+            n = 20
+            s.step(n)
+            f = s.get_populations()
+        rng = np.random.default_rng(int(kn * 1000))
+        cells = [(0, 0, 0), (4095, 4095, 0), (17, 4094, 0)] + [(int(x), int(y), 0) for x, y in rng.integers(0, 4096, (5, 2))]
+        worst = 0.0
+        for c in cells:
+            ref = ob.evolve_window("D2Q37", 4, tau, grid, 1e-3, 1, 1e-6, 1, c, n)
+            got = f[:, c[0] + 4096 * c[1]]
+            worst = max(worst, float(np.max(np.abs(got - ref[p]) / np.abs(ref[p]))))
+        say(f"Kn={kn}: worst sampled rel err {worst:.2e}")
+        assert worst <= 1e-5
