@@ -80,6 +80,25 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
                     bytes_per_step=s.bytes_per_step, ncell=s.ncell)
 
 
+def copy_bandwidth(torch, nbytes, reps=20):
+    """Read+write bandwidth of a plain device-to-device copy of nbytes (torch's copy kernel):
+    the practical HBM ceiling for a kernel that reads and writes each byte once."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
 def cpu_baseline(target_seconds=12.0):
     """The FP64 oracle on a bounded sample of the workload: D2Q37, N = 4, Kn = 0.1 on a
     4096 x 256 slab of the 4096 x 4096 grid (same wave, noise and tau), whole steps."""
@@ -128,6 +147,10 @@ def main():
                            args.steps, args.warmup, noise=1e-6)
     log(f"  {main_res['ms_per_step']:.4f} ms/step, {main_res['mlups']:.0f} MLUPS, {main_res['gbs']:.0f} GB/s")
 
+    log("timing a plain copy of the same bytes ...")
+    copy_gbs, copy_ms = copy_bandwidth(torch, main_res["bytes_per_step"] // 2)
+    log(f"  copy: {copy_gbs:.0f} GB/s ({copy_ms:.3f} ms)")
+
     variants = {}
     if args.variants:
         for name, kw in [
@@ -170,7 +193,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profiles(tag, main_res["bytes_per_step"]),
-                     "kernel": tag, "algorithmic_bytes_per_launch": main_res["bytes_per_step"]},
+                     "kernel": tag, "algorithmic_bytes_per_launch": main_res["bytes_per_step"],
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
     }
     if variants:

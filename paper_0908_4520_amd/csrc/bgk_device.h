@@ -15,9 +15,17 @@
 //   P_N = 1 + s + (s^2 - q)/2 + (s^3 - 3 s q)/6 + (s^4 - 6 s^2 q + 3 q^2)/24 (truncated),
 //   f*_a = f_a - omega (f_a - f^eq_a).
 // In v-space, with e_a = w_a (or 1 when scaled):
-//   v*_a = (1 - omega) v_a + omega e_a (d + rho (P_N(s_a) - 1)),
+//   v^eq_a = e_a (d + rho (P_N(s_a) - 1)),   v*_a = v_a + omega (v^eq_a - v_a),
 // and P_N - 1 is the polynomial a0' + a1 s + a2 s^2 + a3 s^3 + a4 s^4 whose coefficients
 // depend only on q, so each population costs one dot product and a Horner chain.
+// The relaxation keeps v_a with coefficient exactly 1: written as (1 - omega) v + omega v^eq,
+// the rounded 1 - omega and omega would not sum to 1 and every step would scale the state by
+// 1 + O(2^-24), a bias that is large against the slow decay of a shear wave.  For the same
+// reason the equilibrium's mass and linear (momentum) terms are corrected for the rounding of
+// the weights and abscissae to the compute type: with the rounded constants sum_a w_a and
+// sum_a w_a xi_ax^2 differ from 1 by ~1e-8, which the corrections delta0, delta1 (computed at
+// compile time from the rounded values) remove, so the FP32 collision conserves mass and
+// momentum up to rounding noise instead of drifting systematically.
 // With omega = 0 every term added to v_a is an exact zero, so a collisionless step moves
 // the stored values bit for bit.
 #pragma once
@@ -132,11 +140,11 @@ struct Codec<ST_FP16_DEV> {
 
 // m_a: factor from stored value to f_a - a_a; e_a: factor from (f^eq_a - a_a)/w_a to v-space.
 template <class L, int S, int A>
-__device__ __forceinline__ constexpr double moment_factor() {
+constexpr double moment_factor() {
     return Codec<S>::scaled ? L::w[A] : 1.0;
 }
 template <class L, int S, int A>
-__device__ __forceinline__ constexpr double eq_factor() {
+constexpr double eq_factor() {
     return Codec<S>::scaled ? 1.0 : L::w[A];
 }
 
@@ -161,10 +169,26 @@ __device__ __forceinline__ Moments<T> project(const T (&v)[L::Q]) {
     return m;
 }
 
+// Sums of the velocity-set constants after rounding to the compute type T.
+template <class L, class T>
+constexpr double rounded_mass_sum() {
+    double s = 0.0;
+    for (int a = 0; a < L::Q; ++a) s += (double)(T)L::w[a];
+    return s;
+}
+template <class L, class T>
+constexpr double rounded_momentum_sum() {   // sum_a w_a xi_ax^2 (the same for every axis)
+    double s = 0.0;
+    for (int a = 0; a < L::Q; ++a) s += (double)(T)L::w[a] * (double)(T)L::xi[a][0] * (double)(T)L::xi[a][0];
+    return s;
+}
+
 // Relax the Q values in place; omega = 1/tau (0 = collisionless).
 template <class L, int N, int S, class T>
 __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
     static_assert(N >= 1 && N <= 4, "Hermite order 1..4");
+    constexpr double delta0 = 1.0 / rounded_mass_sum<L, T>() - 1.0;
+    constexpr double delta1 = 1.0 / rounded_momentum_sum<L, T>() - 1.0;
     const Moments<T> m = project<L, S>(v);
     const T rho = Codec<S>::dev ? T(1) + m.d : m.d;
     const T inv = T(1) / rho;
@@ -175,13 +199,12 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
     if constexpr (N >= 2) { a0m = T(-0.5) * q; a2 = T(0.5); }
     if constexpr (N >= 3) { a1 = T(1) - T(0.5) * q; }
     if constexpr (N >= 4) { a0m = q * (T(0.125) * q - T(0.5)); a2 = T(0.5) - T(0.25) * q; }
-    const T orho = omega * rho;
-    const T B0 = omega * (m.d + rho * a0m);
-    const T B1 = orho * a1;
-    const T B2 = orho * a2;
-    const T B3 = orho * T(1.0 / 6.0);
-    const T B4 = orho * T(1.0 / 24.0);
-    const T keep = T(1) - omega;
+    const T C0 = (m.d + m.d * T(delta0)) + rho * a0m;
+    const T r1 = rho * a1;
+    const T C1 = r1 + r1 * T(delta1);
+    const T C2 = rho * a2;
+    const T C3 = rho * T(1.0 / 6.0);
+    const T C4 = rho * T(1.0 / 24.0);
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
         T s = T(0);
@@ -189,13 +212,14 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
         if constexpr (L::xi[a][1] != 0.0) s += T(L::xi[a][1]) * uy;
         if constexpr (L::D == 3 && L::xi[a][2] != 0.0) s += T(L::xi[a][2]) * uz;
         T p;
-        if constexpr (N == 1) p = B1;
-        if constexpr (N == 2) p = B1 + s * B2;
-        if constexpr (N == 3) p = B1 + s * (B2 + s * B3);
-        if constexpr (N == 4) p = B1 + s * (B2 + s * (B3 + s * B4));
-        p = B0 + s * p;
+        if constexpr (N == 1) p = C1;
+        if constexpr (N == 2) p = C1 + s * C2;
+        if constexpr (N == 3) p = C1 + s * (C2 + s * C3);
+        if constexpr (N == 4) p = C1 + s * (C2 + s * (C3 + s * C4));
+        p = C0 + s * p;
         constexpr double ef = eq_factor<L, S, a>();
-        v[a] = (ef == 1.0) ? keep * v[a] + p : keep * v[a] + T(ef) * p;
+        const T veq = (ef == 1.0) ? p : T(ef) * p;
+        v[a] = v[a] + omega * (veq - v[a]);
     });
 }
 

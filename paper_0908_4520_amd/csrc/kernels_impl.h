@@ -107,10 +107,34 @@ __global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
 }
 
 // ---------------------------------------------------------------- Beam-Warming, 2-D
-// Thread = one column x walking a strip of `tile` rows.  For each population it keeps the
-// x-advected values of the two upwind rows in registers (sliding window), so every row of
-// every population is x-advected once per strip, plus two halo rows.  The x-neighbours
-// x - s, x - 2s come from neighbouring lanes' loads through L1.
+// Cross-lane moves of one wave (DPP row/wave shifts, gfx9 family):
+//   shr: lane l takes lane l-1's value, lane 0 takes `old`;
+//   shl: lane l takes lane l+1's value, lane 63 takes `old`.
+__device__ __forceinline__ int dpp_shr_i(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl_i(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float dpp_shr(float old, float v) {
+    return __builtin_bit_cast(float, dpp_shr_i(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float dpp_shl(float old, float v) {
+    return __builtin_bit_cast(float, dpp_shl_i(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v)));
+}
+typedef int int2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double dpp_shr(double old, double v) {
+    const int2v o = __builtin_bit_cast(int2v, old), x = __builtin_bit_cast(int2v, v);
+    return __builtin_bit_cast(double, int2v{dpp_shr_i(o.x, x.x), dpp_shr_i(o.y, x.y)});
+}
+__device__ __forceinline__ double dpp_shl(double old, double v) {
+    const int2v o = __builtin_bit_cast(int2v, old), x = __builtin_bit_cast(int2v, v);
+    return __builtin_bit_cast(double, int2v{dpp_shl_i(o.x, x.x), dpp_shl_i(o.y, x.y)});
+}
+
+// Thread = one column x walking a strip of `tile` rows; a wave owns 64 consecutive
+// (aligned) columns.  For each population it keeps the x-advected values of the two
+// upwind rows in registers (sliding window over y).  The x-neighbours x - s, x - 2s come
+// from neighbouring lanes by DPP shifts; the two columns left (right) of the wave come from
+// one extra load per population-row that touches a single cache line and enter the shift as
+// the value of the vacated lane.  So every population-row costs one aligned load, one
+// one-line halo load and three lane shifts; stores are whole aligned wave segments.
 template <class L, int N, int S, bool SR, class T>
 __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
@@ -120,24 +144,34 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     const uint32_t strip = lb / a.per_row;
     const uint32_t xb = lb - strip * a.per_row;
     const int nx = a.nx, ny = a.ny;
-    const int x = (int)(xb * kBlock + threadIdx.x);
-    if (x >= nx) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x0 = (int)(xb * (kBlock / 64) + wv) * 64;
+    if (x0 >= nx) return;                              // whole wave leaves together
+    const int xo = x0 + lane;                          // this lane's column (may exceed nx)
+    const int xl = xo % nx;                            // column it loads (wrapped)
+    const int hl = (x0 - 1 - (lane == 1 ? 1 : 0) + 2 * nx) % nx;   // lane 0: x0-1, lane 1: x0-2
+    const int hr = (x0 + 64 + (lane == 62 ? 1 : 0)) % nx;          // lane 63: x0+64, lane 62: x0+65
+    const bool owner = xo < nx;
     const int y0 = (int)(strip * a.tile);
     const int y1 = min(y0 + (int)a.tile, ny);
     const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
     raw *__restrict__ fout = static_cast<raw *>(a.fout);
     const size_t ps = a.pstride;
-    // wrapped neighbour columns (nx may be 1 or 2: wrap twice)
-    const int xm1 = wrap_once(wrap_once(x - 1, nx), nx), xm2 = wrap_once(wrap_once(x - 2, nx), nx);
-    const int xp1 = wrap_once(wrap_once(x + 1, nx), nx), xp2 = wrap_once(wrap_once(x + 2, nx), nx);
     auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * (size_t)nx; };
     auto xadv = [&](auto I, size_t roff) -> T {
         constexpr int i = decltype(I)::value;
-        constexpr bool px = L::xi[i][0] > 0.0;
         const raw *p = fin + (size_t)i * ps + roff;
-        const T f0 = (T)C::dec(p[x]);
-        const T f1 = (T)C::dec(p[px ? xm1 : xp1]);
-        const T f2 = (T)C::dec(p[px ? xm2 : xp2]);
+        const T f0 = (T)C::dec(p[xl]);
+        T f1, f2;
+        if constexpr (L::xi[i][0] > 0.0) {            // upwind = left: f(x-1), f(x-2)
+            const T h = (T)C::dec(p[hl]);
+            f1 = dpp_shr(h, f0);
+            f2 = dpp_shr(dpp_shl(h, h), f1);
+        } else {                                      // upwind = right: f(x+1), f(x+2)
+            const T h = (T)C::dec(p[hr]);
+            f1 = dpp_shl(h, f0);
+            f2 = dpp_shl(dpp_shr(h, h), f1);
+        }
         return f0 - cf.alpha[0][i] * (f0 - f1) + cf.beta[0][i] * (f1 - f2);
     };
     T A[L::Q], B[L::Q];
@@ -173,12 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
             }
         });
         collide<L, N, S, T>(v, om);
-        const size_t o = r0 + (size_t)x;
-        const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
-        });
+        if (owner) {
+            const size_t o = r0 + (size_t)xo;
+            const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
+            static_for<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            });
+        }
     }
 }
 

@@ -104,7 +104,7 @@ uint64_t splitmix64(uint64_t x) {
 
 // Step-kernel tile choices: chunks of 256 cells per block (shift) or strip rows (Beam-Warming).
 const int kShiftTiles[] = {1, 2, 4, 8};
-const int kBWTiles[] = {8, 16, 32, 4, 64};
+const int kBWTiles[] = {16, 32, 8, 4, 64};
 
 }  // namespace
 
@@ -152,7 +152,7 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     if (s->move == LBM_MOVE_BW2) {
         const uint32_t H = (uint32_t)kBWTiles[tile_index];
         a.tile = H;
-        a.per_row = (nx + kBlock - 1) / kBlock;
+        a.per_row = (nx + kBlock - 1) / kBlock;   // blocks of 4 waves x 64 columns
         a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
     } else if (s->rows_ok) {
         const uint32_t cpt = (uint32_t)kShiftTiles[tile_index];
