@@ -182,6 +182,46 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile,
 /* Information: cells, populations and bytes moved per step (2 Q ncell * bytes per value). */
 lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, int64_t *bytes_per_step);
 
+/* ---- Batches: many independent shear-wave instances advanced together (a Kn sweep).
+ * Every instance is a decaying standing shear wave (as lbm_set_shear_wave with no density
+ * noise) on its own periodic nx x ny grid with its own velocity set, Hermite order and tau.
+ * lbm_batch_run advances all of them by `steps` steps in one persistent kernel launch (each
+ * instance owned by one workgroup, the step loop on the device), replayed from a captured
+ * HIP graph, and records each instance's sine amplitude of u_x (as lbm_shear_amplitude,
+ * wave along y) every record_every steps.  Supported: 2-D sets D2Q9, D2Q37 (exact shift),
+ * D2Q16_GH, D2Q36_GH (Beam-Warming advection at o->cfl); eq_order 1..4; storage
+ * LBM_FP32_DEV or LBM_FP64; wave_axis 1; nz = 1. */
+typedef struct {
+    lbm_lattice lat;
+    int32_t eq_order;
+    double tau;            /* > 1/2, or INFINITY */
+    lbm_grid g;            /* nz = 1 */
+    double u0;             /* amplitude of u_x = u0 sin(2 pi y / ny) at step 0 */
+    int32_t wave_axis;     /* must be 1 */
+} lbm_instance;
+
+typedef struct lbm_batch lbm_batch;
+
+/* Allocates every instance's two population buffers in one device pool and initialises
+ * each instance to its shear wave at step 0.  o may be NULL (storage LBM_FP32_DEV, cfl 0.5);
+ * o->hip_stream NULL means the batch creates its own stream (graph capture needs one). */
+lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t count, const lbm_opts *o);
+/* Every instance back to its shear wave at step 0. */
+lbm_status lbm_batch_reset(lbm_batch *b);
+/* Advance every instance by steps >= 0 steps.  If amp is non-NULL it receives, per instance
+ * in input order, steps / record_every + 1 amplitudes (before the first step, then after
+ * every record_every steps): amp[i * (steps / record_every + 1) + k].  record_every >= 1.
+ * Synchronises before returning. */
+lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, double *amp);
+/* Decoded FP64 populations f[a * ncell + cell] of instance `index` (ncell = nx * ny). */
+lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f);
+/* Time each workgroup size (256, 512, 1024) over `steps` steps, keep the fastest, and restore
+ * the state as it was. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *block, double *ms_per_step);
+/* Total cells and algorithmic bytes per step (2 Q ncell x bytes per value, summed). */
+lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
+void lbm_batch_free(lbm_batch *b);   /* NULL-safe */
+
 /* Thread-local text of the last error (empty string if none). */
 const char *lbm_last_error(void);
 

@@ -25,7 +25,9 @@
 // the weights and abscissae to the compute type: with the rounded constants sum_a w_a and
 // sum_a w_a xi_ax^2 differ from 1 by ~1e-8, which the corrections delta0, delta1 (computed at
 // compile time from the rounded values) remove, so the FP32 collision conserves mass and
-// momentum up to rounding noise instead of drifting systematically.
+// momentum up to rounding noise instead of drifting systematically.  The corrections are
+// below half an ulp of v^eq itself, so they are added to the non-equilibrium difference
+// v^eq - v (small, so finely resolved), not to v^eq or its coefficients.
 // With omega = 0 every term added to v_a is an exact zero, so a collisionless step moves
 // the stored values bit for bit.
 #pragma once
@@ -199,9 +201,9 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
     if constexpr (N >= 2) { a0m = T(-0.5) * q; a2 = T(0.5); }
     if constexpr (N >= 3) { a1 = T(1) - T(0.5) * q; }
     if constexpr (N >= 4) { a0m = q * (T(0.125) * q - T(0.5)); a2 = T(0.5) - T(0.25) * q; }
-    const T C0 = (m.d + m.d * T(delta0)) + rho * a0m;
-    const T r1 = rho * a1;
-    const T C1 = r1 + r1 * T(delta1);
+    const T C0 = m.d + rho * a0m;
+    const T C1 = rho * a1;
+    const T D0 = m.d * T(delta0), D1 = C1 * T(delta1);   // conservation corrections
     const T C2 = rho * a2;
     const T C3 = rho * T(1.0 / 6.0);
     const T C4 = rho * T(1.0 / 24.0);
@@ -217,9 +219,14 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
         if constexpr (N == 3) p = C1 + s * (C2 + s * C3);
         if constexpr (N == 4) p = C1 + s * (C2 + s * (C3 + s * C4));
         p = C0 + s * p;
+        const T corr = D0 + s * D1;
         constexpr double ef = eq_factor<L, S, a>();
-        const T veq = (ef == 1.0) ? p : T(ef) * p;
-        v[a] = v[a] + omega * (veq - v[a]);
+        T neq;                                      // v^eq - v, corrected
+        if constexpr (ef == 1.0)
+            neq = (p - v[a]) + corr;
+        else
+            neq = (T(ef) * p - v[a]) + T(ef) * corr;
+        v[a] = v[a] + omega * neq;
     });
 }
 

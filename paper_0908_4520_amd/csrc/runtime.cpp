@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "kernels.h"
 #include "lattices.inc"
 #include "lbm.h"
@@ -620,6 +621,331 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile,
     s->tile = best;
     if (best_tile) *best_tile = best;
     if (best_ms) *best_ms = (double)best_t / steps_per_trial;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================== batches
+struct lbm_batch {
+    int count = 0;
+    lbm_storage storage = LBM_FP32_DEV;
+    double cfl = 0.5;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<lbm_instance> inst;
+    std::vector<BatchInst> desc;            // host copy of the descriptors
+    std::vector<const KernelSet *> ks;
+    BatchInst *d_inst = nullptr;
+    int32_t *d_order = nullptr;
+    int32_t *d_cur = nullptr;
+    void *pool = nullptr;
+    size_t pool_bytes = 0;
+    double *d_sin = nullptr;
+    double *d_bw = nullptr;
+    double *d_amp = nullptr;
+    size_t amp_cap = 0;                     // doubles allocated in d_amp
+    int block = 1024;
+    int64_t cells = 0, bytes_per_step = 0;
+    // cached graph of one run configuration
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t g_steps = -1;
+    int g_record = -1, g_block = -1, g_first = -1;
+};
+
+namespace {
+
+void batch_drop_graph(lbm_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->g_steps = -1;
+}
+
+lbm_status batch_init_states(lbm_batch *b) {
+    for (int i = 0; i < b->count; ++i) {
+        const BatchInst &d = b->desc[i];
+        WaveArgs a{};
+        a.f = static_cast<char *>(b->pool) + d.off * (size_t)elem_size(b->storage);
+        a.nx = d.nx;
+        a.ny = d.ny;
+        a.nz = 1;
+        a.pstride = d.pstride;
+        a.wave_axis = 1;
+        a.u0 = b->inst[i].u0;
+        a.rho_noise = 0.0;
+        a.seed = 0;
+        a.sin_tab = b->d_sin + d.sin_off;
+        HIP_TRY(b->ks[i]->init_wave(a, b->stream));
+    }
+    std::vector<int32_t> zero(b->count, 0);
+    HIP_TRY(hipMemcpyAsync(b->d_cur, zero.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+lbm_status batch_ensure_amp(lbm_batch *b, size_t n) {
+    if (n <= b->amp_cap) return LBM_OK;
+    if (b->d_amp) HIP_TRY(hipFree(b->d_amp));
+    b->d_amp = nullptr;
+    b->amp_cap = 0;
+    batch_drop_graph(b);                    // the graph refers to the old log
+    HIP_TRY(hipMalloc(&b->d_amp, sizeof(double) * n));
+    b->amp_cap = n;
+    return LBM_OK;
+}
+
+BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t first) {
+    BatchArgs a{};
+    a.inst = b->d_inst;
+    a.order = b->d_order;
+    a.pool = b->pool;
+    a.sin_tab = b->d_sin;
+    a.bw = b->d_bw;
+    a.amp = b->d_amp;
+    a.cur = b->d_cur;
+    a.steps = steps;
+    a.record = record;
+    a.record_first = first;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t count, const lbm_opts *opts) {
+    if (!out || !inst) return fail(LBM_EINVAL, "NULL argument");
+    if (count < 1) return fail(LBM_EINVAL, "count must be >= 1");
+    lbm_opts o;
+    lbm_opts_default(&o);
+    o.storage = LBM_FP32_DEV;
+    if (opts) o = *opts;
+    if (o.storage != LBM_FP32_DEV && o.storage != LBM_FP64)
+        return fail(LBM_EINVAL, "batches store LBM_FP32_DEV or LBM_FP64");
+    if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1]");
+    for (int i = 0; i < count; ++i) {
+        const lbm_instance &q = inst[i];
+        const LatInfo *L = lat_info((int)q.lat);
+        if (!L || !batch_supports((int)q.lat, q.eq_order, (int)o.storage))
+            return fail(LBM_EINVAL, "instance %d: lattice %d / order %d not supported in a batch", i, (int)q.lat, q.eq_order);
+        if (!(q.tau > 0.5)) return fail(LBM_EINVAL, "instance %d: tau must be > 1/2", i);
+        if (q.g.nx < 1 || q.g.ny < 1 || q.g.nz != 1) return fail(LBM_EINVAL, "instance %d: grid must be nx, ny >= 1, nz = 1", i);
+        if ((long long)q.g.nx * q.g.ny > (1ll << 26)) return fail(LBM_EINVAL, "instance %d: more than 2^26 cells", i);
+        if (q.wave_axis != 1) return fail(LBM_EINVAL, "instance %d: wave_axis must be 1", i);
+        if (!isfinite(q.u0)) return fail(LBM_EINVAL, "instance %d: u0 must be finite", i);
+    }
+    lbm_batch *b = new lbm_batch();
+    b->count = count;
+    b->storage = o.storage;
+    b->cfl = o.cfl;
+    b->inst.assign(inst, inst + count);
+    b->desc.resize(count);
+    b->ks.resize(count);
+    const int es = elem_size(o.storage);
+    size_t off = 0, sin_off = 0;
+    std::vector<double> sin_h, bw_h((size_t)count * 4 * kMaxQ, 0.0);
+    for (int i = 0; i < count; ++i) {
+        const lbm_instance &q = inst[i];
+        const LatInfo *L = lat_info((int)q.lat);
+        BatchInst &d = b->desc[i];
+        d.lattice = L->id;
+        d.order = q.eq_order;
+        d.nx = q.g.nx;
+        d.ny = q.g.ny;
+        d.ncell = (uint32_t)(q.g.nx * q.g.ny);
+        d.pstride = (d.ncell + 63) / 64 * 64;
+        d.off = off;
+        off += 2ull * L->Q * d.pstride;
+        off = (off + 63) / 64 * 64;
+        d.sin_off = (uint32_t)sin_off;
+        for (int j = 0; j < q.g.ny; ++j) sin_h.push_back(sin(2.0 * M_PI * (double)j / (double)q.g.ny));
+        sin_off += (size_t)q.g.ny;
+        d.bw_off = (uint32_t)((size_t)i * 4 * kMaxQ);
+        if (!L->on_lattice) {
+            const double lam = o.cfl / L->xi_max;
+            for (int a = 0; a < L->Q; ++a)
+                for (int ax = 0; ax < 2; ++ax) {
+                    const double A = fabs(L->xi[a][ax] * lam), bb = 0.5 * A * (1.0 - A);
+                    bw_h[d.bw_off + (2 * ax + 0) * kMaxQ + a] = A + bb;
+                    bw_h[d.bw_off + (2 * ax + 1) * kMaxQ + a] = bb;
+                }
+        }
+        d.omega = isinf(q.tau) ? 0.0 : 1.0 / q.tau;
+        d.amp_off = 0;
+        b->ks[i] = find_kernels(L->id, q.eq_order, (int)o.storage, 0);
+        b->cells += d.ncell;
+        b->bytes_per_step += 2ll * L->Q * d.ncell * es;
+    }
+    // workgroups take instances largest first (cost ~ Q * cells)
+    std::vector<int32_t> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (long long)lat_info(b->desc[x].lattice)->Q * b->desc[x].ncell >
+               (long long)lat_info(b->desc[y].lattice)->Q * b->desc[y].ncell;
+    });
+    b->pool_bytes = off * (size_t)es;
+    hipError_t e = hipSuccess;
+    if (o.hip_stream) {
+        b->stream = (hipStream_t)o.hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->pool, b->pool_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b->d_inst, sizeof(BatchInst) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_order, sizeof(int32_t) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_cur, sizeof(int32_t) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_sin, sizeof(double) * sin_h.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_bw, sizeof(double) * bw_h.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_sin, sin_h.data(), sizeof(double) * sin_h.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_bw, bw_h.data(), sizeof(double) * bw_h.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->pool, 0, b->pool_bytes, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        lbm_status st = fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "batch allocation: %s", hipGetErrorString(e));
+        lbm_batch_free(b);
+        (void)hipGetLastError();
+        return st;
+    }
+    lbm_status st = batch_init_states(b);
+    if (st != LBM_OK) {
+        lbm_batch_free(b);
+        return st;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_free(lbm_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (void *p : {b->pool, (void *)b->d_inst, (void *)b->d_order, (void *)b->d_cur, (void *)b->d_sin,
+                    (void *)b->d_bw, (void *)b->d_amp})
+        if (p) (void)hipFree(p);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+lbm_status lbm_batch_reset(lbm_batch *b) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    return batch_init_states(b);
+}
+
+lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (cells) *cells = b->cells;
+    if (bytes_per_step) *bytes_per_step = b->bytes_per_step;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, double *amp) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps < 0 || record_every < 1) return fail(LBM_EINVAL, "steps >= 0 and record_every >= 1 required");
+    const int64_t per = steps / record_every + 1;
+    if (amp && per * (int64_t)b->count > (1ll << 31)) return fail(LBM_EINVAL, "amplitude log too large");
+    const int32_t rec = amp ? record_every : 0, first = amp ? 1 : 0;
+    if (amp) {
+        lbm_status st = batch_ensure_amp(b, (size_t)per * b->count);
+        if (st != LBM_OK) return st;
+        bool changed = false;
+        for (int i = 0; i < b->count; ++i) {
+            const uint64_t ao = (uint64_t)i * (uint64_t)per;
+            if (b->desc[i].amp_off != ao) changed = true;
+            b->desc[i].amp_off = ao;
+        }
+        if (changed) batch_drop_graph(b);
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_inst, b->desc.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, b->stream));
+    if (!(b->gexec && b->g_steps == steps && b->g_record == rec && b->g_block == b->block && b->g_first == first)) {
+        batch_drop_graph(b);
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_batch((int)b->storage, b->block, batch_args(b, steps, rec, first), (uint32_t)b->count, b->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        HIP_TRY(e);
+        HIP_TRY(e2);
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        b->g_steps = steps;
+        b->g_record = rec;
+        b->g_block = b->block;
+        b->g_first = first;
+    }
+    HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+    if (amp) HIP_TRY(hipMemcpyAsync(amp, b->d_amp, sizeof(double) * per * b->count, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
+    if (!b || !f) return fail(LBM_EINVAL, "NULL argument");
+    if (index < 0 || index >= b->count) return fail(LBM_EINVAL, "index out of range");
+    const BatchInst &d = b->desc[index];
+    const LatInfo *L = lat_info(d.lattice);
+    int32_t cur = 0;
+    HIP_TRY(hipMemcpyAsync(&cur, b->d_cur + index, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const size_t es = (size_t)elem_size(b->storage);
+    const void *base = static_cast<char *>(b->pool) + (d.off + (size_t)cur * L->Q * d.pstride) * es;
+    double *t = nullptr;
+    HIP_TRY(hipMalloc(&t, sizeof(double) * d.ncell));
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < L->Q && e == hipSuccess; ++a) {
+        const double add = is_dev(b->storage) ? L->w[a] : 0.0;
+        e = b->ks[index]->decode(base, d.pstride, d.ncell, a, add, 1.0, t, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(f + (size_t)a * d.ncell, t, sizeof(double) * d.ncell, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    (void)hipFree(t);
+    HIP_TRY(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *block, double *ms_per_step) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    void *save = nullptr;
+    HIP_TRY(hipMalloc(&save, b->pool_bytes));
+    std::vector<int32_t> cur_h(b->count);
+    hipError_t e = hipMemcpyAsync(save, b->pool, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cur_h.data(), b->d_cur, sizeof(int32_t) * b->count, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, b->desc.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, b->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = b->block;
+    float best_ms = 1e30f;
+    for (int blk : {1024, 512, 256}) {
+        if (e != hipSuccess) break;
+        e = launch_batch((int)b->storage, blk, batch_args(b, 1, 0, 0), (uint32_t)b->count, b->stream);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = launch_batch((int)b->storage, blk, batch_args(b, steps, 0, 0), (uint32_t)b->count, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = blk;
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->pool, save, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_cur, cur_h.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    HIP_TRY(e);
+    if (best != b->block) batch_drop_graph(b);
+    b->block = best;
+    if (block) *block = best;
+    if (ms_per_step) *ms_per_step = (double)best_ms / steps;
     return LBM_OK;
 }
 

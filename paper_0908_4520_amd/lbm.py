@@ -33,6 +33,11 @@ class lbm_opts(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("check_every", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
+class lbm_instance(ctypes.Structure):
+    _fields_ = [("lat", ctypes.c_int), ("eq_order", ctypes.c_int32), ("tau", ctypes.c_double), ("g", lbm_grid),
+                ("u0", ctypes.c_double), ("wave_axis", ctypes.c_int32)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lbm error {code}: {msg}")
@@ -72,6 +77,14 @@ SIGNATURES = {
     "lbm_set_tile": (ctypes.c_int, [_SIM, ctypes.c_int32]),
     "lbm_autotune": (ctypes.c_int, [_SIM, ctypes.c_int32, _I32, _D]),
     "lbm_sizes": (ctypes.c_int, [_SIM, _I64, _I32, _I32, _I64]),
+    "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(lbm_opts)]),
+    "lbm_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _D]),
+    "lbm_batch_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D]),
+    "lbm_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _I32, _D]),
+    "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
+    "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -245,3 +258,65 @@ class Sim:
         t, ms = ctypes.c_int32(), ctypes.c_double()
         _check(_lib.lbm_autotune(self._h, steps_per_trial, ctypes.byref(t), ctypes.byref(ms)))
         return t.value, ms.value
+
+
+class Batch:
+    """Owner of one lbm_batch*: many shear-wave instances advanced in one persistent launch.
+
+    instances: iterable of (lattice, eq_order, tau, (nx, ny), u0)."""
+
+    def __init__(self, instances, storage: str = "fp32_dev", cfl: float = 0.5, stream=None):
+        inst = list(instances)
+        arr = (lbm_instance * len(inst))()
+        for k, (lat, N, tau, (nx, ny), u0) in enumerate(inst):
+            arr[k] = lbm_instance(LATTICES[lat], N, float(tau), lbm_grid(nx, ny, 1), float(u0), 1)
+        o = lbm_opts_default()
+        o.storage = STORAGES[storage]
+        o.cfl = cfl
+        o.hip_stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.lbm_batch_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(inst), ctypes.byref(o)))
+        self._h = h
+        self.count = len(inst)
+        self.instances = inst
+        c, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.lbm_batch_sizes(h, ctypes.byref(c), ctypes.byref(b)))
+        self.cells, self.bytes_per_step = c.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbm_batch_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self):
+        _check(_lib.lbm_batch_reset(self._h))
+
+    def run(self, steps: int, record_every: int = 1, record: bool = True):
+        """Advance every instance; returns amp[count, steps // record_every + 1] or None."""
+        if not record:
+            _check(_lib.lbm_batch_run(self._h, steps, record_every, None))
+            return None
+        per = steps // record_every + 1
+        amp = np.empty((self.count, per))
+        _check(_lib.lbm_batch_run(self._h, steps, record_every, _dp(amp)))
+        return amp
+
+    def populations(self, index: int) -> np.ndarray:
+        lat, _, _, (nx, ny), _ = self.instances[index]
+        Q = {"D2Q9": 9, "D2Q37": 37, "D2Q16-GH": 16, "D2Q36-GH": 36}[lat]
+        f = np.empty((Q, nx * ny))
+        _check(_lib.lbm_batch_populations(self._h, index, _dp(f)))
+        return f
+
+    def autotune(self, steps: int = 20):
+        b, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.lbm_batch_autotune(self._h, steps, ctypes.byref(b), ctypes.byref(ms)))
+        return b.value, ms.value
