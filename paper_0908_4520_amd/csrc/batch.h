@@ -17,20 +17,38 @@ struct BatchInst {
     double omega;
 };
 
+// A run of consecutive cells of one instance, updated by one workgroup (one cell per thread).
+struct BatchChunk {
+    int32_t inst;
+    uint32_t start, count;
+};
+
 struct BatchArgs {
     const BatchInst *inst;
-    const int32_t *order;       // workgroup b runs instance order[b]
+    const int32_t *order;       // per-instance form: workgroup b runs instance order[b]
     void *pool;
     const double *sin_tab;
     const double *bw;
     double *amp;                // amplitude log
-    int32_t *cur;               // per instance: buffer holding the state (read at start, written at end)
+    const int32_t *cur;         // per instance: buffer holding the state when the launch starts
     int64_t steps;
     int32_t record;             // record every this many steps (0 = never)
     int32_t record_first;       // also record before the first step
+    // grid form
+    const BatchChunk *chunks;   // chunks, grouped by instance
+    const uint32_t *inst_first; // chunks of instance i: [inst_first[i], inst_first[i+1])
+    const uint32_t *wg_first;   // chunks of workgroup b: wg_chunks[wg_first[b] .. wg_first[b+1])
+    const uint32_t *wg_chunks;
+    uint32_t nwg;               // workgroups of the grid form
+    uint32_t nrec;              // amplitudes per instance in this run
+    uint32_t *barrier;          // device-wide barrier counter (zeroed before the launch)
+    int32_t *abort;             // set if a barrier wait exceeded its bound
+    double *partials;           // per chunk and record: FP64 sums
 };
 
-hipError_t launch_batch(int storage, int block, const BatchArgs &a, uint32_t count, hipStream_t s);
+// form 0: one workgroup per instance; form 1: chunks over a resident grid with a barrier per step.
+hipError_t launch_batch(int storage, int form, int block, const BatchArgs &a, uint32_t count, hipStream_t s);
+int batch_grid_resident_per_cu(int storage, int block);
 bool batch_supports(int lattice, int order, int storage);
 
 }  // namespace lbm

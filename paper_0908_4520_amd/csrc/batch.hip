@@ -1,11 +1,18 @@
 // batch.hip -- many independent shear-wave instances advanced in one persistent launch.
 //
-// Each workgroup owns one instance (2-D velocity set, nx x ny periodic grid, its own tau and
-// Hermite order) for the whole run: it loops over the steps on the device, pulling from one
-// of the instance's two buffers and writing the other, with a workgroup barrier between
-// steps.  An instance never spans two workgroups, so no synchronisation leaves the CU.  Every
-// `record` steps the workgroup reduces the sine projection of u_x over its cells in FP64 and
-// stores it in the amplitude log.  Instances are handed to workgroups largest first.
+// Two persistent forms, chosen by timing (lbm_batch_autotune):
+//  * per-instance: each workgroup owns one whole instance for the run and loops over the
+//    steps with a workgroup barrier between them; nothing synchronises across CUs, but the
+//    run lasts as long as the largest instance takes on one CU;
+//  * grid: every instance is cut into chunks of one cell per thread, the chunks are spread
+//    over a grid that is small enough to be resident at once (largest-cost-first onto the
+//    least-loaded workgroup), and all workgroups meet at a device-wide barrier after every
+//    step.  The barrier spins on an agent-scope counter with a bounded number of sleeps; if
+//    the bound is hit (workgroups not resident together) it raises an abort flag that every
+//    workgroup checks, so all of them leave the loop and the host reports the failure.
+// Amplitudes: the sine projection of u_x is summed in FP64 per chunk (fixed order) and the
+// per-instance sums are formed by a second kernel in a fixed order, so runs are bitwise
+// reproducible.
 #include "batch.h"
 #include "kernels_impl.h"
 
@@ -27,102 +34,97 @@ constexpr int kQuadXm1 = 3 | (0 << 2) | (1 << 4) | (2 << 6);   // lane i <- i-1 
 constexpr int kQuadXp1 = 1 | (2 << 2) | (3 << 4) | (0 << 6);   // lane i <- i+1 (mod 4): value at x+1
 constexpr int kQuadX2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);    // lane i <- i+2 (mod 4): value at x+-2
 
-// QUAD: nx == 4, x-neighbours by quad rotation; otherwise by loads.
-template <class L, int N, int S, bool BW, bool QUAD, int BLOCK>
-__device__ __forceinline__ void run_instance(const BatchInst &in, const BatchArgs &a, double *red) {
+template <class L, int S>
+__device__ __forceinline__ typename Codec<S>::raw *inst_buffer(const BatchInst &in, const BatchArgs &a, int which) {
+    return static_cast<typename Codec<S>::raw *>(a.pool) + in.off + (size_t)which * L::Q * in.pstride;
+}
+
+// One step for cells [start, start + count) of an instance, one cell per thread (count <= the
+// block size; with nx = 4 the start is a multiple of 4, so quads are whole rows).
+template <class L, int N, int S, bool BW, bool QUAD>
+__device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs &a, int cur, uint32_t start,
+                                           uint32_t count) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;
+    if (threadIdx.x >= count) return;
+    const raw *__restrict__ src = inst_buffer<L, S>(in, a, cur);
+    raw *__restrict__ dst = inst_buffer<L, S>(in, a, cur ^ 1);
     const int nx = in.nx, ny = in.ny;
-    const uint32_t ncell = in.ncell;
     const size_t ps = in.pstride;
-    raw *buf[2] = {static_cast<raw *>(a.pool) + in.off, static_cast<raw *>(a.pool) + in.off + (size_t)L::Q * ps};
-    const int32_t idx = a.order[blockIdx.x];
-    int cur = a.cur[idx];
-    const T om = (T)in.omega;
-    const double *sin_tab = a.sin_tab + in.sin_off;
-    const int tid = threadIdx.x;
-
-    auto record = [&](int k) {
-        const raw *f = buf[cur];
-        double acc = 0.0;
-        for (uint32_t cell = tid; cell < ncell; cell += BLOCK) {
-            double dsum = 0.0, jx = 0.0;
-            static_for<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                constexpr double mf = moment_factor<L, S, i>();
-                const double g = mf * C::dec64(f[(size_t)i * ps + cell]);
-                dsum += g;
-                if constexpr (L::xi[i][0] != 0.0) jx += L::xi[i][0] * g;
-            });
-            const double rho = C::dev ? 1.0 + dsum : dsum;
-            acc += (jx / rho) * sin_tab[cell / (uint32_t)nx];
-        }
-        const double s = wave_sum(acc);
-        if ((tid & 63) == 0) red[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
-            a.amp[in.amp_off + (size_t)k] = 2.0 * t / (double)ncell;
-        }
-        __syncthreads();
-    };
-
-    if (a.record_first) record(0);
-    for (int64_t step = 0; step < a.steps; ++step) {
-        const raw *__restrict__ src = buf[cur];
-        raw *__restrict__ dst = buf[cur ^ 1];
-        for (uint32_t base = 0; base < ncell; base += BLOCK) {
-            const uint32_t cell = base + (uint32_t)tid;
-            // nx = 4 and BLOCK % 4 == 0: quads are whole rows, active or inactive together
-            if (cell >= ncell) continue;
-            const int x = (int)(cell % (uint32_t)nx), y = (int)(cell / (uint32_t)nx);
-            T v[L::Q];
-            if constexpr (!BW) {
-                static_for<L::Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny);
-                    v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
-                });
-            } else {
-                static_for<L::Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    constexpr bool px = L::xi[i][0] > 0.0, py = L::xi[i][1] > 0.0;
-                    const T ax = (T)a.bw[in.bw_off + 0 * kMaxQ + i], bx = (T)a.bw[in.bw_off + 1 * kMaxQ + i];
-                    const T ay = (T)a.bw[in.bw_off + 2 * kMaxQ + i], by = (T)a.bw[in.bw_off + 3 * kMaxQ + i];
-                    const int r0 = y, r1 = imod(py ? y - 1 : y + 1, ny), r2 = imod(py ? y - 2 : y + 2, ny);
-                    const raw *p = src + (size_t)i * ps;
-                    T xa[3];
-                    const int rows[3] = {r0, r1, r2};
+    const uint32_t cell = start + threadIdx.x;
+    const int x = (int)(cell % (uint32_t)nx), y = (int)(cell / (uint32_t)nx);
+    T v[L::Q];
+    if constexpr (!BW) {
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny);
+            v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
+        });
+    } else {
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr bool px = L::xi[i][0] > 0.0, py = L::xi[i][1] > 0.0;
+            const T ax = (T)a.bw[in.bw_off + 0 * kMaxQ + i], bx = (T)a.bw[in.bw_off + 1 * kMaxQ + i];
+            const T ay = (T)a.bw[in.bw_off + 2 * kMaxQ + i], by = (T)a.bw[in.bw_off + 3 * kMaxQ + i];
+            const int rows[3] = {y, imod(py ? y - 1 : y + 1, ny), imod(py ? y - 2 : y + 2, ny)};
+            const raw *p = src + (size_t)i * ps;
+            T xa[3];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const raw *pr = p + (size_t)rows[k] * nx;
-                        const T f0 = (T)C::dec(pr[x]);
-                        T f1, f2;
-                        if constexpr (QUAD) {
-                            f1 = px ? quad_move<kQuadXm1>(f0) : quad_move<kQuadXp1>(f0);
-                            f2 = quad_move<kQuadX2>(f0);
-                        } else {
-                            f1 = (T)C::dec(pr[imod(px ? x - 1 : x + 1, nx)]);
-                            f2 = (T)C::dec(pr[imod(px ? x - 2 : x + 2, nx)]);
-                        }
-                        xa[k] = f0 - ax * (f0 - f1) + bx * (f1 - f2);
-                    }
-                    v[i] = xa[0] - ay * (xa[0] - xa[1]) + by * (xa[1] - xa[2]);
-                });
+            for (int k = 0; k < 3; ++k) {
+                const raw *pr = p + (size_t)rows[k] * nx;
+                const T f0 = (T)C::dec(pr[x]);
+                T f1, f2;
+                if constexpr (QUAD) {
+                    f1 = px ? quad_move<kQuadXm1>(f0) : quad_move<kQuadXp1>(f0);
+                    f2 = quad_move<kQuadX2>(f0);
+                } else {
+                    f1 = (T)C::dec(pr[imod(px ? x - 1 : x + 1, nx)]);
+                    f2 = (T)C::dec(pr[imod(px ? x - 2 : x + 2, nx)]);
+                }
+                xa[k] = f0 - ax * (f0 - f1) + bx * (f1 - f2);
             }
-            collide<L, N, S, T>(v, om);
-            static_for<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                dst[(size_t)i * ps + cell] = C::template enc<false>(v[i], 0u);
-            });
-        }
-        __syncthreads();
-        cur ^= 1;
-        if (a.record > 0 && (step + 1) % a.record == 0) record((int)((step + 1) / a.record));
+            v[i] = xa[0] - ay * (xa[0] - xa[1]) + by * (xa[1] - xa[2]);
+        });
     }
-    if (tid == 0) a.cur[idx] = cur;
+    collide<L, N, S, T>(v, (T)in.omega);
+    static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        dst[(size_t)i * ps + cell] = C::template enc<false>(v[i], 0u);
+    });
+}
+
+// Workgroup sum over cells [start, start + count) of u_x sin(2 pi y / ny), FP64, fixed order.
+// Every thread of the block must call it; the result is valid in thread 0.
+template <class L, int S, int BLOCK>
+__device__ double partial_amp(const BatchInst &in, const BatchArgs &a, int cur, uint32_t start, uint32_t count,
+                              double *red) {
+    using C = Codec<S>;
+    const auto *f = inst_buffer<L, S>(in, a, cur);
+    const size_t ps = in.pstride;
+    const double *sin_tab = a.sin_tab + in.sin_off;
+    double acc = 0.0;
+    for (uint32_t t = threadIdx.x; t < count; t += BLOCK) {
+        const uint32_t cell = start + t;
+        double dsum = 0.0, jx = 0.0;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr double mf = moment_factor<L, S, i>();
+            const double g = mf * C::dec64(f[(size_t)i * ps + cell]);
+            dsum += g;
+            if constexpr (L::xi[i][0] != 0.0) jx += L::xi[i][0] * g;
+        });
+        const double rho = C::dev ? 1.0 + dsum : dsum;
+        acc += (jx / rho) * sin_tab[cell / (uint32_t)in.nx];
+    }
+    const double s = wave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
+    return t;
 }
 
 // Kind of an instance: 4 * set + (N - 1), set 0 = D2Q9, 1 = D2Q37, 2 = D2Q16-GH, 3 = D2Q36-GH;
@@ -132,59 +134,178 @@ __host__ __device__ inline int batch_kind(int lattice, int order, int nx) {
     return 4 * set + (order - 1) + ((set >= 2 && nx == 4) ? 16 : 0);
 }
 
-template <int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
-    __shared__ double red[BLOCK / 64];
-    const BatchInst in = a.inst[a.order[blockIdx.x]];
+#define LBM_BATCH_KINDS(X)                                                                           \
+    X(0, D2Q9, 1, false, false) X(1, D2Q9, 2, false, false) X(2, D2Q9, 3, false, false)              \
+    X(3, D2Q9, 4, false, false) X(4, D2Q37, 1, false, false) X(5, D2Q37, 2, false, false)            \
+    X(6, D2Q37, 3, false, false) X(7, D2Q37, 4, false, false) X(8, D2Q16_GH, 1, true, false)         \
+    X(9, D2Q16_GH, 2, true, false) X(10, D2Q16_GH, 3, true, false) X(11, D2Q16_GH, 4, true, false)   \
+    X(12, D2Q36_GH, 1, true, false) X(13, D2Q36_GH, 2, true, false) X(14, D2Q36_GH, 3, true, false)  \
+    X(15, D2Q36_GH, 4, true, false) X(24, D2Q16_GH, 1, true, true) X(25, D2Q16_GH, 2, true, true)    \
+    X(26, D2Q16_GH, 3, true, true) X(27, D2Q16_GH, 4, true, true) X(28, D2Q36_GH, 1, true, true)     \
+    X(29, D2Q36_GH, 2, true, true) X(30, D2Q36_GH, 3, true, true) X(31, D2Q36_GH, 4, true, true)
+
+template <int S>
+__device__ __forceinline__ void step_chunk(const BatchInst &in, const BatchArgs &a, int cur, uint32_t start,
+                                           uint32_t count) {
     switch (batch_kind(in.lattice, in.order, in.nx)) {
-#define LBM_CASE(K, L, N, BW, QUAD) \
-    case K: run_instance<L, N, S, BW, QUAD, BLOCK>(in, a, red); break;
-        LBM_CASE(0, D2Q9, 1, false, false)
-        LBM_CASE(1, D2Q9, 2, false, false)
-        LBM_CASE(2, D2Q9, 3, false, false)
-        LBM_CASE(3, D2Q9, 4, false, false)
-        LBM_CASE(4, D2Q37, 1, false, false)
-        LBM_CASE(5, D2Q37, 2, false, false)
-        LBM_CASE(6, D2Q37, 3, false, false)
-        LBM_CASE(7, D2Q37, 4, false, false)
-        LBM_CASE(8, D2Q16_GH, 1, true, false)
-        LBM_CASE(9, D2Q16_GH, 2, true, false)
-        LBM_CASE(10, D2Q16_GH, 3, true, false)
-        LBM_CASE(11, D2Q16_GH, 4, true, false)
-        LBM_CASE(12, D2Q36_GH, 1, true, false)
-        LBM_CASE(13, D2Q36_GH, 2, true, false)
-        LBM_CASE(14, D2Q36_GH, 3, true, false)
-        LBM_CASE(15, D2Q36_GH, 4, true, false)
-        LBM_CASE(24, D2Q16_GH, 1, true, true)
-        LBM_CASE(25, D2Q16_GH, 2, true, true)
-        LBM_CASE(26, D2Q16_GH, 3, true, true)
-        LBM_CASE(27, D2Q16_GH, 4, true, true)
-        LBM_CASE(28, D2Q36_GH, 1, true, true)
-        LBM_CASE(29, D2Q36_GH, 2, true, true)
-        LBM_CASE(30, D2Q36_GH, 3, true, true)
-        LBM_CASE(31, D2Q36_GH, 4, true, true)
-#undef LBM_CASE
+#define LBM_STEP_CASE(K, L, N, BW, QUAD) \
+    case K: step_cells<L, N, S, BW, QUAD>(in, a, cur, start, count); break;
+        LBM_BATCH_KINDS(LBM_STEP_CASE)
+#undef LBM_STEP_CASE
         default: break;
     }
 }
 
 template <int S, int BLOCK>
-hipError_t launch_batch_t(const BatchArgs &a, uint32_t count, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch<S, BLOCK>), dim3(count), dim3(BLOCK), 0, s, a);
+__device__ __forceinline__ double amp_chunk(const BatchInst &in, const BatchArgs &a, int cur, uint32_t start,
+                                            uint32_t count, double *red) {
+    switch (in.lattice) {
+        case D2Q9::id: return partial_amp<D2Q9, S, BLOCK>(in, a, cur, start, count, red);
+        case D2Q37::id: return partial_amp<D2Q37, S, BLOCK>(in, a, cur, start, count, red);
+        case D2Q16_GH::id: return partial_amp<D2Q16_GH, S, BLOCK>(in, a, cur, start, count, red);
+        default: return partial_amp<D2Q36_GH, S, BLOCK>(in, a, cur, start, count, red);
+    }
+}
+
+// ---------------------------------------------------------------- per-instance form
+template <int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
+    __shared__ double red[BLOCK / 64];
+    const int32_t idx = a.order[blockIdx.x];
+    const BatchInst in = a.inst[idx];
+    int cur = a.cur[idx];
+    auto record = [&](int k) {
+        const double s = amp_chunk<S, BLOCK>(in, a, cur, 0, in.ncell, red);
+        if (threadIdx.x == 0) a.amp[in.amp_off + (size_t)k] = 2.0 * s / (double)in.ncell;
+    };
+    if (a.record_first) record(0);
+    for (int64_t step = 0; step < a.steps; ++step) {
+        for (uint32_t base = 0; base < in.ncell; base += BLOCK)
+            step_chunk<S>(in, a, cur, base, min((uint32_t)BLOCK, in.ncell - base));
+        __syncthreads();
+        cur ^= 1;
+        if (a.record > 0 && (step + 1) % a.record == 0) record((int)((step + 1) / a.record));
+    }
+}
+
+// ---------------------------------------------------------------- grid form
+constexpr uint32_t kSpinLimit = 1u << 26;   // sleeps of ~50 ns: seconds, far beyond any real step
+
+// Device-wide barrier number `gen` (1, 2, ...).  Returns false if the run was aborted.
+__device__ bool grid_barrier(const BatchArgs &a, uint32_t gen, int *flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // release this workgroup's stores to every CU
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = gen * a.nwg;
+        uint32_t spins = 0;
+        int ab = 0;
+        while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) break;
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins >= kSpinLimit) {
+                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+        }
+        __threadfence();   // acquire: later loads see every workgroup's stores
+        *flag = ab;
+    }
+    __syncthreads();
+    return *flag == 0;
+}
+
+template <int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
+    __shared__ double red[BLOCK / 64];
+    __shared__ int flag;
+    const uint32_t c0 = a.wg_first[blockIdx.x], c1 = a.wg_first[blockIdx.x + 1];
+    auto record = [&](int k, int64_t done) {
+        for (uint32_t c = c0; c < c1; ++c) {
+            const BatchChunk ch = a.chunks[a.wg_chunks[c]];
+            const BatchInst in = a.inst[ch.inst];
+            const int cur = a.cur[ch.inst] ^ (int)(done & 1);
+            const double s = amp_chunk<S, BLOCK>(in, a, cur, ch.start, ch.count, red);
+            if (threadIdx.x == 0) a.partials[(size_t)a.wg_chunks[c] * a.nrec + k] = s;
+        }
+    };
+    if (a.record_first) record(0, 0);
+    uint32_t gen = 0;
+    for (int64_t step = 0; step < a.steps; ++step) {
+        for (uint32_t c = c0; c < c1; ++c) {
+            const BatchChunk ch = a.chunks[a.wg_chunks[c]];
+            const BatchInst in = a.inst[ch.inst];
+            step_chunk<S>(in, a, a.cur[ch.inst] ^ (int)(step & 1), ch.start, ch.count);
+        }
+        if (!grid_barrier(a, ++gen, &flag)) return;
+        if (a.record > 0 && (step + 1) % a.record == 0) record((int)((step + 1) / a.record), step + 1);
+    }
+}
+
+// amp[i][k] = 2 / ncell_i * sum over the chunks of instance i (in order) of partials[c][k].
+__global__ __launch_bounds__(256) void k_batch_amp(BatchArgs a, uint32_t count) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (uint64_t)count * a.nrec) return;
+    const uint32_t i = (uint32_t)(t / a.nrec), k = (uint32_t)(t % a.nrec);
+    double s = 0.0;
+    for (uint32_t c = a.inst_first[i]; c < a.inst_first[i + 1]; ++c) s += a.partials[(size_t)c * a.nrec + k];
+    a.amp[a.inst[i].amp_off + k] = 2.0 * s / (double)a.inst[i].ncell;
+}
+
+__global__ void k_batch_reset(BatchArgs a) {
+    if (threadIdx.x == 0) {
+        *a.barrier = 0u;
+        *a.abort = 0;
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+template <int S, int BLOCK>
+hipError_t launch_t(int form, const BatchArgs &a, uint32_t count, hipStream_t s) {
+    if (form == 0) {
+        hipLaunchKernelGGL((k_batch<S, BLOCK>), dim3(count), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_grid<S, BLOCK>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess || (a.record <= 0 && !a.record_first)) return e;
+    const uint64_t n = (uint64_t)count * a.nrec;
+    hipLaunchKernelGGL(k_batch_amp, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, a, count);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int storage, int block, const BatchArgs &a, uint32_t count, hipStream_t s) {
-    if (storage == ST_FP32_DEV) {
-        if (block == 256) return launch_batch_t<ST_FP32_DEV, 256>(a, count, s);
-        if (block == 512) return launch_batch_t<ST_FP32_DEV, 512>(a, count, s);
-        if (block == 1024) return launch_batch_t<ST_FP32_DEV, 1024>(a, count, s);
-    } else if (storage == ST_FP64) {
-        if (block == 256) return launch_batch_t<ST_FP64, 256>(a, count, s);
-        if (block == 512) return launch_batch_t<ST_FP64, 512>(a, count, s);
-        if (block == 1024) return launch_batch_t<ST_FP64, 1024>(a, count, s);
-    }
+template <int S>
+hipError_t launch_s(int form, int block, const BatchArgs &a, uint32_t count, hipStream_t s) {
+    if (block == 256) return launch_t<S, 256>(form, a, count, s);
+    if (block == 512) return launch_t<S, 512>(form, a, count, s);
+    if (block == 1024) return launch_t<S, 1024>(form, a, count, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(int storage, int form, int block, const BatchArgs &a, uint32_t count, hipStream_t s) {
+    if (storage == ST_FP32_DEV) return launch_s<ST_FP32_DEV>(form, block, a, count, s);
+    if (storage == ST_FP64) return launch_s<ST_FP64>(form, block, a, count, s);
+    return hipErrorInvalidValue;
+}
+
+template <int S, int BLOCK>
+int resident_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_grid<S, BLOCK>, BLOCK, 0) != hipSuccess) return 0;
+    return n;
+}
+
+int batch_grid_resident_per_cu(int storage, int block) {
+    if (storage == ST_FP32_DEV)
+        return block == 256 ? resident_t<ST_FP32_DEV, 256>() : block == 512 ? resident_t<ST_FP32_DEV, 512>()
+                                                                            : resident_t<ST_FP32_DEV, 1024>();
+    return block == 256 ? resident_t<ST_FP64, 256>() : block == 512 ? resident_t<ST_FP64, 512>()
+                                                                     : resident_t<ST_FP64, 1024>();
 }
 
 bool batch_supports(int lattice, int order, int storage) {

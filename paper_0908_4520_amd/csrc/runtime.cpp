@@ -636,6 +636,7 @@ struct lbm_batch {
     std::vector<lbm_instance> inst;
     std::vector<BatchInst> desc;            // host copy of the descriptors
     std::vector<const KernelSet *> ks;
+    std::vector<int32_t> cur;               // buffer holding each instance's state
     BatchInst *d_inst = nullptr;
     int32_t *d_order = nullptr;
     int32_t *d_cur = nullptr;
@@ -645,13 +646,23 @@ struct lbm_batch {
     double *d_bw = nullptr;
     double *d_amp = nullptr;
     size_t amp_cap = 0;                     // doubles allocated in d_amp
-    int block = 1024;
+    int form = 0;                           // 0: workgroup per instance, 1: chunks + grid barrier
+    int block = 512;
     int64_t cells = 0, bytes_per_step = 0;
+    // grid-form plan (for plan_block)
+    int plan_block = 0;
+    uint32_t nchunks = 0, nwg = 0;
+    BatchChunk *d_chunks = nullptr;
+    uint32_t *d_inst_first = nullptr, *d_wg_first = nullptr, *d_wg_chunks = nullptr;
+    uint32_t *d_barrier = nullptr;
+    int32_t *d_abort = nullptr;
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
     // cached graph of one run configuration
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t g_steps = -1;
-    int g_record = -1, g_block = -1, g_first = -1;
+    int g_record = -1, g_block = -1, g_first = -1, g_form = -1;
 };
 
 namespace {
@@ -680,24 +691,103 @@ lbm_status batch_init_states(lbm_batch *b) {
         a.sin_tab = b->d_sin + d.sin_off;
         HIP_TRY(b->ks[i]->init_wave(a, b->stream));
     }
-    std::vector<int32_t> zero(b->count, 0);
-    HIP_TRY(hipMemcpyAsync(b->d_cur, zero.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream));
+    std::fill(b->cur.begin(), b->cur.end(), 0);
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBM_OK;
 }
 
-lbm_status batch_ensure_amp(lbm_batch *b, size_t n) {
-    if (n <= b->amp_cap) return LBM_OK;
-    if (b->d_amp) HIP_TRY(hipFree(b->d_amp));
-    b->d_amp = nullptr;
-    b->amp_cap = 0;
-    batch_drop_graph(b);                    // the graph refers to the old log
-    HIP_TRY(hipMalloc(&b->d_amp, sizeof(double) * n));
-    b->amp_cap = n;
+template <class P>
+lbm_status realloc_dev(P **p, size_t bytes) {
+    if (*p) HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    HIP_TRY(hipMalloc((void **)p, bytes));
     return LBM_OK;
 }
 
-BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t first) {
+// Chunks of `block` cells per instance; chunks spread over the resident grid, each chunk
+// (largest cost first) onto the least-loaded workgroup.
+lbm_status batch_plan(lbm_batch *b, int block) {
+    if (b->plan_block == block) return LBM_OK;
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = batch_grid_resident_per_cu((int)b->storage, block);
+    if (per_cu < 1 || ncu < 1) return fail(LBM_EDEVICE, "grid form cannot be resident with %d threads", block);
+    std::vector<BatchChunk> chunks;
+    std::vector<uint32_t> inst_first(b->count + 1, 0);
+    std::vector<double> cost;
+    for (int i = 0; i < b->count; ++i) {
+        inst_first[i] = (uint32_t)chunks.size();
+        const BatchInst &d = b->desc[i];
+        const LatInfo *L = lat_info(d.lattice);
+        const double per_cell = (double)L->Q * (L->on_lattice ? 1.0 : 2.5);
+        for (uint32_t s0 = 0; s0 < d.ncell; s0 += (uint32_t)block) {
+            const uint32_t n = std::min<uint32_t>((uint32_t)block, d.ncell - s0);
+            chunks.push_back(BatchChunk{i, s0, n});
+            cost.push_back(per_cell * n);
+        }
+    }
+    inst_first[b->count] = (uint32_t)chunks.size();
+    const uint32_t nchunks = (uint32_t)chunks.size();
+    const uint32_t nwg = std::min<uint32_t>(nchunks, (uint32_t)(per_cu * ncu));
+    std::vector<uint32_t> idx(nchunks);
+    for (uint32_t k = 0; k < nchunks; ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nwg, 0.0);
+    std::vector<std::vector<uint32_t>> lists(nwg);
+    for (uint32_t k : idx) {
+        uint32_t best = 0;
+        for (uint32_t w = 1; w < nwg; ++w)
+            if (load[w] < load[best]) best = w;
+        load[best] += cost[k];
+        lists[best].push_back(k);
+    }
+    std::vector<uint32_t> wg_first(nwg + 1, 0), wg_chunks;
+    for (uint32_t w = 0; w < nwg; ++w) {
+        std::sort(lists[w].begin(), lists[w].end());
+        wg_first[w] = (uint32_t)wg_chunks.size();
+        wg_chunks.insert(wg_chunks.end(), lists[w].begin(), lists[w].end());
+    }
+    wg_first[nwg] = (uint32_t)wg_chunks.size();
+    lbm_status st;
+    if ((st = realloc_dev(&b->d_chunks, sizeof(BatchChunk) * nchunks)) != LBM_OK) return st;
+    if ((st = realloc_dev(&b->d_inst_first, sizeof(uint32_t) * inst_first.size())) != LBM_OK) return st;
+    if ((st = realloc_dev(&b->d_wg_first, sizeof(uint32_t) * wg_first.size())) != LBM_OK) return st;
+    if ((st = realloc_dev(&b->d_wg_chunks, sizeof(uint32_t) * wg_chunks.size())) != LBM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(b->d_chunks, chunks.data(), sizeof(BatchChunk) * nchunks, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_inst_first, inst_first.data(), sizeof(uint32_t) * inst_first.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_wg_first, wg_first.data(), sizeof(uint32_t) * wg_first.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_wg_chunks, wg_chunks.data(), sizeof(uint32_t) * wg_chunks.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->nchunks = nchunks;
+    b->nwg = nwg;
+    b->plan_block = block;
+    b->partials_cap = 0;
+    batch_drop_graph(b);
+    return LBM_OK;
+}
+
+lbm_status batch_ensure_logs(lbm_batch *b, size_t per) {
+    const size_t n_amp = per * (size_t)b->count;
+    if (n_amp > b->amp_cap) {
+        lbm_status st = realloc_dev(&b->d_amp, sizeof(double) * n_amp);
+        if (st != LBM_OK) return st;
+        b->amp_cap = n_amp;
+        batch_drop_graph(b);
+    }
+    if (b->form == 1) {
+        const size_t n_part = per * (size_t)b->nchunks;
+        if (n_part > b->partials_cap) {
+            lbm_status st = realloc_dev(&b->d_partials, sizeof(double) * n_part);
+            if (st != LBM_OK) return st;
+            b->partials_cap = n_part;
+            batch_drop_graph(b);
+        }
+    }
+    return LBM_OK;
+}
+
+BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t first, uint32_t nrec) {
     BatchArgs a{};
     a.inst = b->d_inst;
     a.order = b->d_order;
@@ -709,7 +799,25 @@ BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t 
     a.steps = steps;
     a.record = record;
     a.record_first = first;
+    a.chunks = b->d_chunks;
+    a.inst_first = b->d_inst_first;
+    a.wg_first = b->d_wg_first;
+    a.wg_chunks = b->d_wg_chunks;
+    a.nwg = b->nwg;
+    a.nrec = nrec;
+    a.barrier = b->d_barrier;
+    a.abort = b->d_abort;
+    a.partials = b->d_partials;
     return a;
+}
+
+lbm_status batch_check_abort(lbm_batch *b) {
+    if (b->form != 1) return LBM_OK;
+    int32_t ab = 0;
+    HIP_TRY(hipMemcpyAsync(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (ab) return fail(LBM_EDEVICE, "batch grid barrier timed out: workgroups were not resident together");
+    return LBM_OK;
 }
 
 }  // namespace
@@ -744,6 +852,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     b->inst.assign(inst, inst + count);
     b->desc.resize(count);
     b->ks.resize(count);
+    b->cur.assign(count, 0);
     const int es = elem_size(o.storage);
     size_t off = 0, sin_off = 0;
     std::vector<double> sin_h, bw_h((size_t)count * 4 * kMaxQ, 0.0);
@@ -779,7 +888,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
         b->cells += d.ncell;
         b->bytes_per_step += 2ll * L->Q * d.ncell * es;
     }
-    // workgroups take instances largest first (cost ~ Q * cells)
+    // per-instance form: workgroups take instances largest first (cost ~ Q * cells)
     std::vector<int32_t> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -800,6 +909,8 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     if (e == hipSuccess) e = hipMalloc(&b->d_cur, sizeof(int32_t) * count);
     if (e == hipSuccess) e = hipMalloc(&b->d_sin, sizeof(double) * sin_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_bw, sizeof(double) * bw_h.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_barrier, sizeof(uint32_t) * 2);
+    if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_sin, sin_h.data(), sizeof(double) * sin_h.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_bw, bw_h.data(), sizeof(double) * bw_h.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, b->stream);
@@ -825,7 +936,9 @@ void lbm_batch_free(lbm_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
     for (void *p : {b->pool, (void *)b->d_inst, (void *)b->d_order, (void *)b->d_cur, (void *)b->d_sin,
-                    (void *)b->d_bw, (void *)b->d_amp})
+                    (void *)b->d_bw, (void *)b->d_amp, (void *)b->d_chunks, (void *)b->d_inst_first,
+                    (void *)b->d_wg_first, (void *)b->d_wg_chunks, (void *)b->d_barrier, (void *)b->d_abort,
+                    (void *)b->d_partials})
         if (p) (void)hipFree(p);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -846,26 +959,28 @@ lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_pe
 lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, double *amp) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
     if (steps < 0 || record_every < 1) return fail(LBM_EINVAL, "steps >= 0 and record_every >= 1 required");
-    const int64_t per = steps / record_every + 1;
-    if (amp && per * (int64_t)b->count > (1ll << 31)) return fail(LBM_EINVAL, "amplitude log too large");
+    const int64_t per = amp ? steps / record_every + 1 : 1;
+    if (per * (int64_t)b->count > (1ll << 31)) return fail(LBM_EINVAL, "amplitude log too large");
     const int32_t rec = amp ? record_every : 0, first = amp ? 1 : 0;
-    if (amp) {
-        lbm_status st = batch_ensure_amp(b, (size_t)per * b->count);
-        if (st != LBM_OK) return st;
-        bool changed = false;
-        for (int i = 0; i < b->count; ++i) {
-            const uint64_t ao = (uint64_t)i * (uint64_t)per;
-            if (b->desc[i].amp_off != ao) changed = true;
-            b->desc[i].amp_off = ao;
-        }
-        if (changed) batch_drop_graph(b);
+    lbm_status st;
+    if (b->form == 1 && (st = batch_plan(b, b->block)) != LBM_OK) return st;
+    if ((st = batch_ensure_logs(b, (size_t)per)) != LBM_OK) return st;
+    bool changed = false;
+    for (int i = 0; i < b->count; ++i) {
+        const uint64_t ao = (uint64_t)i * (uint64_t)per;
+        if (b->desc[i].amp_off != ao) changed = true;
+        b->desc[i].amp_off = ao;
     }
+    if (changed) batch_drop_graph(b);
     HIP_TRY(hipMemcpyAsync(b->d_inst, b->desc.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, b->stream));
-    if (!(b->gexec && b->g_steps == steps && b->g_record == rec && b->g_block == b->block && b->g_first == first)) {
+    HIP_TRY(hipMemcpyAsync(b->d_cur, b->cur.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream));
+    if (!(b->gexec && b->g_steps == steps && b->g_record == rec && b->g_block == b->block && b->g_first == first &&
+          b->g_form == b->form)) {
         batch_drop_graph(b);
         HIP_TRY(hipStreamSynchronize(b->stream));
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_batch((int)b->storage, b->block, batch_args(b, steps, rec, first), (uint32_t)b->count, b->stream);
+        hipError_t e = launch_batch((int)b->storage, b->form, b->block, batch_args(b, steps, rec, first, (uint32_t)per),
+                                    (uint32_t)b->count, b->stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         HIP_TRY(e);
@@ -876,10 +991,14 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
         b->g_record = rec;
         b->g_block = b->block;
         b->g_first = first;
+        b->g_form = b->form;
     }
     HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
     if (amp) HIP_TRY(hipMemcpyAsync(amp, b->d_amp, sizeof(double) * per * b->count, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
+    if ((st = batch_check_abort(b)) != LBM_OK) return st;
+    if (steps & 1)
+        for (auto &c : b->cur) c ^= 1;
     return LBM_OK;
 }
 
@@ -888,11 +1007,8 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
     if (index < 0 || index >= b->count) return fail(LBM_EINVAL, "index out of range");
     const BatchInst &d = b->desc[index];
     const LatInfo *L = lat_info(d.lattice);
-    int32_t cur = 0;
-    HIP_TRY(hipMemcpyAsync(&cur, b->d_cur + index, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
     const size_t es = (size_t)elem_size(b->storage);
-    const void *base = static_cast<char *>(b->pool) + (d.off + (size_t)cur * L->Q * d.pstride) * es;
+    const void *base = static_cast<char *>(b->pool) + (d.off + (size_t)b->cur[index] * L->Q * d.pstride) * es;
     double *t = nullptr;
     HIP_TRY(hipMalloc(&t, sizeof(double) * d.ncell));
     hipError_t e = hipSuccess;
@@ -907,45 +1023,77 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
     return LBM_OK;
 }
 
-lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *block, double *ms_per_step) {
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_t *block, double *ms_per_step) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     void *save = nullptr;
     HIP_TRY(hipMalloc(&save, b->pool_bytes));
-    std::vector<int32_t> cur_h(b->count);
     hipError_t e = hipMemcpyAsync(save, b->pool, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(cur_h.data(), b->d_cur, sizeof(int32_t) * b->count, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, b->desc.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_cur, b->cur.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    int best = b->block;
+    int best_form = b->form, best_block = b->block;
     float best_ms = 1e30f;
-    for (int blk : {1024, 512, 256}) {
-        if (e != hipSuccess) break;
-        e = launch_batch((int)b->storage, blk, batch_args(b, 1, 0, 0), (uint32_t)b->count, b->stream);   // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess) e = launch_batch((int)b->storage, blk, batch_args(b, steps, 0, 0), (uint32_t)b->count, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = blk;
+    lbm_status st = LBM_OK;
+    for (int form : {0, 1}) {
+        for (int blk : {1024, 512, 256}) {
+            if (e != hipSuccess || st != LBM_OK) break;
+            if (form == 1) {
+                if (batch_grid_resident_per_cu((int)b->storage, blk) < 1) continue;
+                if ((st = batch_plan(b, blk)) != LBM_OK) break;
+            }
+            const int saved_form = b->form;
+            b->form = form;
+            const BatchArgs a1 = batch_args(b, 1, 0, 0, 1), an = batch_args(b, steps, 0, 0, 1);
+            b->form = saved_form;
+            e = launch_batch((int)b->storage, form, blk, a1, (uint32_t)b->count, b->stream);   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) e = launch_batch((int)b->storage, form, blk, an, (uint32_t)b->count, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            int32_t ab = 0;
+            if (e == hipSuccess && form == 1) {
+                e = hipMemcpy(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost);
+            }
+            if (e == hipSuccess && !ab && ms < best_ms) {
+                best_ms = ms;
+                best_form = form;
+                best_block = blk;
+            }
         }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b->pool, save, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_cur, cur_h.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(save);
     HIP_TRY(e);
-    if (best != b->block) batch_drop_graph(b);
-    b->block = best;
-    if (block) *block = best;
+    if (st != LBM_OK) return st;
+    batch_drop_graph(b);
+    b->form = best_form;
+    b->block = best_block;
+    if (b->form == 1 && (st = batch_plan(b, b->block)) != LBM_OK) return st;
+    if (form) *form = best_form;
+    if (block) *block = best_block;
     if (ms_per_step) *ms_per_step = (double)best_ms / steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if ((form != 0 && form != 1) || (block != 256 && block != 512 && block != 1024))
+        return fail(LBM_EINVAL, "form must be 0 or 1 and block 256, 512 or 1024");
+    if (form == 1) {
+        lbm_status st = batch_plan(b, block);
+        if (st != LBM_OK) return st;
+    }
+    batch_drop_graph(b);
+    b->form = form;
+    b->block = block;
     return LBM_OK;
 }
 

@@ -82,7 +82,8 @@ SIGNATURES = {
     "lbm_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "lbm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _D]),
     "lbm_batch_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D]),
-    "lbm_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _I32, _D]),
+    "lbm_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _I32, _I32, _D]),
+    "lbm_batch_set_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -317,6 +318,10 @@ class Batch:
         return f
 
     def autotune(self, steps: int = 20):
-        b, ms = ctypes.c_int32(), ctypes.c_double()
-        _check(_lib.lbm_batch_autotune(self._h, steps, ctypes.byref(b), ctypes.byref(ms)))
-        return b.value, ms.value
+        """Returns (form, block, ms per step) of the fastest choice, which is kept."""
+        f, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.lbm_batch_autotune(self._h, steps, ctypes.byref(f), ctypes.byref(b), ctypes.byref(ms)))
+        return f.value, b.value, ms.value
+
+    def set_form(self, form: int, block: int):
+        _check(_lib.lbm_batch_set_form(self._h, form, block))

@@ -35,7 +35,8 @@ SMALL = [("D2Q9", 2, 0.3, 4, 40), ("D2Q37", 4, 0.05, 4, 50), ("D2Q16-GH", 3, 1.0
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32_dev"])
-def test_small_mixed_batch_matches_oracle(storage):
+@pytest.mark.parametrize("form,block", [(0, 256), (0, 1024), (1, 256), (1, 512)])
+def test_small_mixed_batch_matches_oracle(storage, form, block):
     lbm = need_gpu()
     inst = []
     for lat, N, kn, nx, ny in SMALL:
@@ -43,6 +44,7 @@ def test_small_mixed_batch_matches_oracle(storage):
         inst.append((lat, N, tau, (nx, ny), A0))
     steps, every = 40, 10
     with lbm.Batch(inst, storage=storage) as b:
+        b.set_form(form, block)
         amp = b.run(steps, every)
         pops = [b.populations(i) for i in range(len(inst))]
     tol_a = 1e-12 if storage == "fp64" else 1e-5
@@ -51,16 +53,19 @@ def test_small_mixed_batch_matches_oracle(storage):
         ref, r = _oracle_series(lat, N, tau, nx, ny, steps, every)
         da = float(np.max(np.abs(amp[i] - ref))) / A0
         df = float(np.max(np.abs(pops[i] - r.f[perm(lat)]) / np.abs(r.f[perm(lat)])))
-        say(f"batch {storage} {lat} N={N} {nx}x{ny}: |dA|/A0 {da:.2e}, pops {df:.2e}")
+        say(f"batch {storage} form {form}/{block} {lat} N={N} {nx}x{ny}: |dA|/A0 {da:.2e}, pops {df:.2e}")
         assert da <= tol_a and df <= tol_f
 
 
-def test_batch_graph_replay_equals_one_long_run():
+@pytest.mark.parametrize("form", [0, 1])
+def test_batch_graph_replay_equals_one_long_run(form):
     """Two replays of the captured 20-step graph (with host work between) give exactly the
-    populations of one 40-step run."""
+    populations of one 40-step run, in either persistent form, and the forms agree."""
     lbm = need_gpu()
     inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, kn, nx, ny in SMALL if not math.isinf(kn)]
     with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(form, 512)
+        b.set_form(1 - form, 256)
         a.run(20, 5)
         _ = [a.populations(i) for i in range(2)]
         a.run(20, 5)
@@ -76,8 +81,8 @@ def test_batch_autotune_keeps_state():
     with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
         a.run(7, 7)
         b.run(7, 7)
-        blk, ms = a.autotune(5)
-        assert blk in (256, 512, 1024) and ms > 0
+        form, blk, ms = a.autotune(5)
+        assert form in (0, 1) and blk in (256, 512, 1024) and ms > 0
         a.run(9, 3)
         b.run(9, 3)
         for i in range(len(inst)):
@@ -109,10 +114,10 @@ def test_config5_kn_sweep_256_instances_5000_steps():
     inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, nx, ny, kn in w]
     steps, every = 5000, 50
     with lbm.Batch(inst) as b:
-        blk, ms = b.autotune(20)
+        form, blk, ms = b.autotune(20)
         b.reset()
         amp = b.run(steps, every)
-    say(f"config5: block {blk}, {ms:.4f} ms/step autotune")
+    say(f"config5: form {form} block {blk}, {ms:.4f} ms/step autotune")
     ns = np.arange(0, steps + 1, every)
     errs = []
     gam_err = []
