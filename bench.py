@@ -6,7 +6,11 @@ grid, decaying standing shear wave u_x = 1e-3 sin(2 pi y / 4096) with uniform de
 A step is one launch of the fused shift-moments-equilibrium-relaxation kernel over every
 cell.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--variants]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-variants]
+
+Besides the main workload the JSON line carries "variants": the 512^3 D3Q39 step with FP32,
+BF16 and FP16 deviation storage (stochastic rounding), the D2Q16-GH DVM step at 2048^2, the
+full-f FP32 ablation, the 4 x 64 D2Q9 FP64 case, and the 256-instance batched Kn sweep.
 """
 from __future__ import annotations
 
@@ -37,9 +41,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str, per_launch_algorithmic: float):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the
-    current kernel sources; otherwise None."""
+def traffic_from_profiles(kernel_tag: str, tile: int):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE counters, scaled by a plain copy of known
+    size) from the committed counter summary for this kernel and tile, if the counters were
+    taken on the current kernel sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -48,7 +53,8 @@ def traffic_from_profiles(kernel_tag: str, per_launch_algorithmic: float):
     ent = data.get(kernel_tag)
     if not ent or ent.get("source_digest") != kernel_source_digest():
         return None
-    return ent.get("bytes_per_launch")
+    t = ent.get("per_tile", {}).get(str(tile))
+    return None if t is None else t.get("bytes_per_launch")
 
 
 def time_steps(sim, steps, stream, torch):
@@ -78,6 +84,31 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
         gbs = s.bytes_per_step / (ms * 1e-3) / 1e9
         return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, frac=gbs / HBM_PEAK_GBS, tile=tile,
                     bytes_per_step=s.bytes_per_step, ncell=s.ncell)
+
+
+def run_batch(lbm, torch, stream, steps=5000, record_every=50):
+    """The Kn sweep: 256 shear-wave instances (seed 0) in one persistent launch per run."""
+    from paper_0908_4520_amd import workloads
+    inst = []
+    for lat, N, nx, ny, kn in workloads.batch_instances(0, 256):
+        inst.append((lat, N, lbm.lbm_tau_from_kn(lat, kn, ny, cfl=0.5), (nx, ny), 1e-3))
+    with lbm.Batch(inst, stream=stream.cuda_stream) as b:
+        form, block, _ = b.autotune(20)
+        b.reset()
+        b.run(10, record_every)                       # warm-up (captures the graph)
+        b.reset()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        b.run(steps, record_every)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        return dict(ms_per_step=ms / steps, mlups=b.cells * steps / (ms * 1e-3) / 1e6,
+                    gbs=b.bytes_per_step * steps / (ms * 1e-3) / 1e9, cells=b.cells, steps=steps,
+                    form=form, block=block, bytes_per_step=b.bytes_per_step,
+                    note="effective GB/s: the 115 MB state is resident in the 256 MB Infinity Cache")
 
 
 def copy_bandwidth(torch, nbytes, reps=20):
@@ -127,7 +158,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", action="store_true", help="also time the other storages and sets")
+    ap.add_argument("--no-variants", action="store_true", help="time only the main workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,18 +183,25 @@ def main():
     log(f"  copy: {copy_gbs:.0f} GB/s ({copy_ms:.3f} ms)")
 
     variants = {}
-    if args.variants:
+    if not args.no_variants:
         for name, kw in [
-            ("D3Q39_512^3_fp32_dev", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp32_dev", axis=2)),
-            ("D3Q39_512^3_bf16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="bf16_dev", axis=2, sr=True)),
-            ("D3Q39_512^3_fp16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp16_dev", axis=2, sr=True)),
-            ("D2Q16-GH_2048^2_fp32_dev", dict(lattice="D2Q16-GH", N=3, kn=1.0, grid=(2048, 2048, 1), storage="fp32_dev", axis=1)),
-            ("D2Q37_4096^2_fp32", dict(lattice="D2Q37", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32", axis=1, noise=1e-6)),
+            ("D3Q39_512^3_N4_fp32_dev", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp32_dev", axis=2)),
+            ("D3Q39_512^3_N4_bf16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="bf16_dev", axis=2, sr=True)),
+            ("D3Q39_512^3_N4_fp16_dev_sr", dict(lattice="D3Q39", N=4, kn=0.05, grid=(512, 512, 512), storage="fp16_dev", axis=2, sr=True)),
+            ("D2Q16-GH_2048^2_N3_bw2_fp32_dev", dict(lattice="D2Q16-GH", N=3, kn=1.0, grid=(2048, 2048, 1), storage="fp32_dev", axis=1)),
+            ("D2Q37_4096^2_N4_fp32_full", dict(lattice="D2Q37", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32", axis=1, noise=1e-6)),
+            ("D2Q9_4x64_N2_fp64", dict(lattice="D2Q9", N=2, kn=0.1, grid=(4, 64, 1), storage="fp64", axis=1)),
         ]:
             log(f"timing {name} ...")
-            r = run_variant(lbm, torch, stream, steps=min(args.steps, 200), warmup=5, **kw)
+            steps = 2000 if name.startswith("D2Q9") else min(args.steps, 200)
+            r = run_variant(lbm, torch, stream, steps=steps, warmup=5, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS, {r['gbs']:.0f} GB/s")
+        log("timing the 256-instance batch (5000 steps) ...")
+        r = run_batch(lbm, torch, stream)
+        variants["batch_256_instances_5000_steps_fp32_dev"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                                               for k, v in r.items()}
+        log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS (form {r['form']}, block {r['block']})")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -192,7 +230,7 @@ def main():
                    "tile": main_res["tile"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(tag, main_res["bytes_per_step"]),
+                     "traffic": traffic_from_profiles(tag, main_res["tile"]),
                      "kernel": tag, "algorithmic_bytes_per_launch": main_res["bytes_per_step"],
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
