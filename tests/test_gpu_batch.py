@@ -102,7 +102,7 @@ def _linear_series(lat, tau, ny, steps, every):
     return np.array(out)
 
 
-def test_config5_kn_sweep_256_instances_5000_steps():
+def test_kn_sweep_256_instances_5000_steps():
     """256 instances (seed 0: ny in [32, 1024], D2Q9 / D2Q16-GH / D2Q36-GH / D2Q37, Kn
     log-uniform in [0.01, 10], nx = 4), FP32 deviations, 5000 steps, amplitude every 50 steps.
     Every series against the linear single-mode prediction (O(u0^2) and FP32 tolerance
@@ -117,7 +117,7 @@ def test_config5_kn_sweep_256_instances_5000_steps():
         form, blk, ms = b.autotune(20)
         b.reset()
         amp = b.run(steps, every)
-    say(f"config5: form {form} block {blk}, {ms:.4f} ms/step autotune")
+    say(f"Kn sweep: form {form} block {blk}, {ms:.4f} ms/step autotune")
     ns = np.arange(0, steps + 1, every)
     errs = []
     gam_err = []
@@ -132,7 +132,7 @@ def test_config5_kn_sweep_256_instances_5000_steps():
             gam_err.append((abs(g_b - g_l) / g_l, i))
     errs = np.array(errs)
     worst = np.argsort(errs)[::-1][:8]
-    say(f"config5: worst |A - A_linear|/A0 {errs.max():.2e}; decay-rate errors over {len(gam_err)} instances: "
+    say(f"Kn sweep: worst |A - A_linear|/A0 {errs.max():.2e}; decay-rate errors over {len(gam_err)} instances: "
         f"max {max(gam_err)[0]:.2e} (instance {max(gam_err)[1]}) median {np.median([g for g, _ in gam_err]):.2e}")
     for i in worst:
         lat, N, tau, (nx, ny), _ = inst[i]
@@ -150,5 +150,5 @@ def test_config5_kn_sweep_256_instances_5000_steps():
         err = float(np.max(np.abs(amp[i] - ref))) / A0
         lin_err = float(np.max(np.abs(_linear_series(lat, tau, ny, steps, every) - ref))) / A0
         worst_oracle = max(worst_oracle, err)
-        say(f"config5 instance {i} {lat} ny={ny} tau={tau:.5g}: |dA|/A0 vs oracle {err:.2e} (oracle vs linear {lin_err:.2e})")
+        say(f"Kn sweep instance {i} {lat} ny={ny} tau={tau:.5g}: |dA|/A0 vs oracle {err:.2e} (oracle vs linear {lin_err:.2e})")
     assert worst_oracle <= 1e-5

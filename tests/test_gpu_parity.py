@@ -42,7 +42,7 @@ def test_library_loads_and_reports_sizes():
         assert s.tile_count() == 4
 
 
-def test_config1_d2q9_fp64_2000_steps():
+def test_d2q9_4x64_fp64_2000_steps():
     """D2Q9, N = 2, FP64, 4 x 64, Kn = 0.1 (tau = 2.2642...), 2000 steps."""
     lbm = need_gpu()
     tau = lbm.lbm_tau_from_kn("D2Q9", 0.1, 64)
@@ -58,7 +58,7 @@ def test_config1_d2q9_fp64_2000_steps():
         assert abs(a_gpu[0] - a_ref[0]) <= 1e-12 * A0, (n, a_gpu, a_ref)
         assert abs(a_gpu[1] - a_ref[1]) <= 1e-12 * A0
     err = rel_err(s.get_populations(), r.f[p])
-    say(f"config1 max rel err {err:.3e}")
+    say(f"D2Q9 4x64 FP64 max rel err {err:.3e}")
     assert err <= 1e-12
 
 

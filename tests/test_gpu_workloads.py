@@ -44,7 +44,7 @@ def _series_oracle(ref, axis, steps, every):
 
 
 @pytest.mark.parametrize("kn", [0.01, 0.1, 1.0])
-def test_config2_d2q37_4096_500_steps(kn):
+def test_d2q37_4096sq_500_steps(kn):
     """D2Q37, N = 4, FP32 deviations, 4096 x 4096, 500 steps: amplitude series within
     1e-5 A0 of the oracle (noise-free run against the oracle column; noisy run against the
     same column within the same tolerance)."""
@@ -61,7 +61,7 @@ def test_config2_d2q37_4096_500_steps(kn):
             if noise == 0.0:
                 f = s.get_populations()
         err = float(np.max(np.abs(a_gpu - a_ref))) / A0
-        say(f"config2 Kn={kn} noise={noise}: A(500)/A0 gpu {a_gpu[-1] / A0:.7f} oracle {a_ref[-1] / A0:.7f}, "
+        say(f"D2Q37 4096^2 Kn={kn} noise={noise}: A(500)/A0 gpu {a_gpu[-1] / A0:.7f} oracle {a_ref[-1] / A0:.7f}, "
             f"max |dA|/A0 = {err:.2e}")
         assert err <= 1e-5
     # populations of every column equal the oracle column within 1e-5 relative
@@ -73,7 +73,7 @@ def test_config2_d2q37_4096_500_steps(kn):
 
 
 @pytest.mark.parametrize("kn", [0.1, 1.0, 10.0])
-def test_config3_dvm_d2q16_gh_2048_1000_steps(kn):
+def test_dvm_d2q16_gh_2048sq_1000_steps(kn):
     """D2Q16 Gauss-Hermite product (off-lattice), N = 3, Beam-Warming at CFL 0.5, 2048 x 2048,
     FP32 deviations, 1000 steps: amplitude series within 1e-5 A0 of the oracle column."""
     lbm = need_gpu()
@@ -87,7 +87,7 @@ def test_config3_dvm_d2q16_gh_2048_1000_steps(kn):
         a_gpu, _ = _series_gpu(s, 1, 1000, 100)
         f = s.get_populations().reshape(16, 2048, 2048)
     err = float(np.max(np.abs(a_gpu - a_ref))) / A0
-    say(f"config3 Kn={kn}: A(1000)/A0 gpu {a_gpu[-1] / A0:.7f} oracle {a_ref[-1] / A0:.7f}, max |dA|/A0 = {err:.2e}")
+    say(f"D2Q16-GH 2048^2 Kn={kn}: A(1000)/A0 gpu {a_gpu[-1] / A0:.7f} oracle {a_ref[-1] / A0:.7f}, max |dA|/A0 = {err:.2e}")
     assert err <= 1e-5
     p = perm("D2Q16-GH")
     fcol = ref.f[p]
@@ -95,7 +95,7 @@ def test_config3_dvm_d2q16_gh_2048_1000_steps(kn):
         assert np.max(np.abs(f[:, :, x] - fcol) / np.abs(fcol)) <= 1e-5
 
 
-def test_config3_sampled_cells_with_noise():
+def test_dvm_2048sq_sampled_cells_with_noise():
     """Noisy DVM run (breaks x-uniformity, exercises the x-advection): sampled cells after
     12 steps against the oracle's dependence-cone evaluation."""
     lbm = need_gpu()
@@ -112,7 +112,7 @@ def test_config3_sampled_cells_with_noise():
         r = ob.evolve_window("D2Q16-GH", 3, tau, grid, A0, 1, 1e-6, 1, c, n, "bw2", 0.5)
         got = f[:, c[0] + 2048 * c[1]]
         worst = max(worst, float(np.max(np.abs(got - r[p]) / np.abs(r[p]))))
-    say(f"config3 sampled cells (noise): worst rel err {worst:.2e}")
+    say(f"D2Q16-GH 2048^2 sampled cells (noise): worst rel err {worst:.2e}")
     assert worst <= 1e-5
 
 
@@ -127,7 +127,7 @@ STORAGES = [("fp32_dev", False, 1e-4), ("fp16_dev", True, 1e-4), ("bf16_dev", Tr
 
 
 @pytest.fixture(scope="module")
-def config4_oracle():
+def d3q39_column_oracle():
     lbm = need_gpu()
     tau = lbm.lbm_tau_from_kn("D3Q39", 0.05, 512)
     ref = ob.BGK("D3Q39", 4, tau, (1, 1, 512))
@@ -139,16 +139,16 @@ def config4_oracle():
 
 
 @pytest.mark.parametrize("storage,sr,tol", STORAGES)
-def test_config4_d3q39_512cubed_decay_rate(config4_oracle, storage, sr, tol):
+def test_d3q39_512cubed_decay_rate(d3q39_column_oracle, storage, sr, tol):
     lbm = need_gpu()
-    tau, a_ref, ns, n_first, g_ref = config4_oracle
+    tau, a_ref, ns, n_first, g_ref = d3q39_column_oracle
     with lbm.Sim("D3Q39", 4, tau, (512, 512, 512), storage=storage, stochastic_round=sr, sr_seed=2024) as s:
         s.set_shear_wave(A0, 2)
         a_gpu, _ = _series_gpu(s, 2, 200, 5)
     g = lbm.lbm_fit_decay(a_gpu, ns, n_first, 200)
     rel = abs(g - g_ref) / g_ref
     amp_err = float(np.max(np.abs(a_gpu - a_ref))) / A0
-    say(f"config4 {storage}{' SR' if sr else ' RNE'}: gamma {g:.8e} oracle {g_ref:.8e} rel err {rel:.2e}; "
+    say(f"D3Q39 512^3 {storage}{' SR' if sr else ' RNE'}: gamma {g:.8e} oracle {g_ref:.8e} rel err {rel:.2e}; "
         f"max |dA|/A0 {amp_err:.2e}")
     if tol is not None:
         assert rel <= tol
