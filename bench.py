@@ -15,7 +15,6 @@ full-f FP32 ablation, the 4 x 64 D2Q9 FP64 case, and the 256-instance batched Kn
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -33,27 +32,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    for name in ("bgk_device.h", "kernels_impl.h", "kernels.h", "lattices.inc"):
-        with open(os.path.join(ROOT, "paper_0908_4520_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def traffic_from_profiles(kernel_tag: str, tile: int):
+def traffic_from_profiles(kernel_tag: str, shape: str):
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE counters, scaled by a plain copy of known
-    size) from the committed counter summary for this kernel and tile, if the counters were
-    taken on the current kernel sources; otherwise None."""
+    size) from the committed counter summary for this kernel and launch shape, if the counters
+    were taken on the current kernel sources; otherwise None."""
+    from paper_0908_4520_amd import counters
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(kernel_tag)
-    if not ent or ent.get("source_digest") != kernel_source_digest():
+    if not ent or ent.get("source_digest") != counters.kernel_source_digest():
         return None
-    t = ent.get("per_tile", {}).get(str(tile))
+    t = ent.get("per_shape", {}).get(shape)
     return None if t is None else t.get("bytes_per_launch")
 
 
@@ -71,18 +63,21 @@ def time_steps(sim, steps, stream, torch):
 
 
 def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, warmup, sr=False, noise=0.0):
+    from paper_0908_4520_amd import counters
     n_w = grid[axis]
     tau = lbm.lbm_tau_from_kn(lattice, kn, n_w)
     with lbm.Sim(lattice, N, tau, grid, storage=storage, stream=stream.cuda_stream, stochastic_round=sr,
                  sr_seed=12345) as s:
         s.set_shear_wave(1e-3, axis, rho_noise=noise, seed=1)
         tile, _ = s.autotune(3)
+        info = s.tile_info(tile)
         s.set_shear_wave(1e-3, axis, rho_noise=noise, seed=1)
         s.step(warmup)
         ms = time_steps(s, steps, stream, torch)
         mlups = s.ncell / (ms * 1e-3) / 1e6
         gbs = s.bytes_per_step / (ms * 1e-3) / 1e9
         return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, frac=gbs / HBM_PEAK_GBS, tile=tile,
+                    shape=counters.shape_key(info["block"], info["blocks"], info["nontemporal"]),
                     bytes_per_step=s.bytes_per_step, ncell=s.ncell)
 
 
@@ -142,7 +137,7 @@ def cpu_baseline(target_seconds=12.0):
     t0 = time.perf_counter()
     sim.step(1)
     one = time.perf_counter() - t0
-    steps = max(1, min(50, int(target_seconds / max(one, 1e-3))))
+    steps = max(1, min(2000, int(target_seconds / max(one, 1e-3))))
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
@@ -227,10 +222,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "D2Q37 N=4 shear wave 4096x4096, Kn=0.1, rho noise 1e-6 seed 1, FP32 deviation storage",
                    "lattice": "D2Q37", "eq_order": 4, "grid": [4096, 4096, 1], "storage": "fp32_dev",
-                   "tile": main_res["tile"], "parallelism": "single GPU"},
+                   "tile": main_res["tile"], "launch_shape": main_res["shape"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(tag, main_res["tile"]),
+                     "traffic": traffic_from_profiles(tag, main_res["shape"]),
                      "kernel": tag, "algorithmic_bytes_per_launch": main_res["bytes_per_step"],
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,

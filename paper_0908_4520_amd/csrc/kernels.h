@@ -22,7 +22,7 @@ struct StepArgs {
     int32_t nx, ny, nz;
     uint32_t pstride;      // elements between consecutive population planes
     uint32_t per_row;      // shift rows kernel: blocks per row; bw2: blocks per strip row
-    uint32_t tile;         // shift rows kernel: 256-cell chunks per block; bw2: rows per strip
+    uint32_t tile;         // shift rows kernel: block-size chunks per block; bw2: rows per strip
     uint32_t nblocks;      // grid size (1-D)
     uint32_t sr_key;       // per-step key of the stochastic-rounding stream
     double omega;          // 1/tau (0 = collisionless)
@@ -74,7 +74,8 @@ using FiniteFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell,
 // Everything for one (lattice, N, storage, rounding) combination.
 struct KernelSet {
     int lattice, order, storage, sr;
-    StepFn shift_rows;     // on-lattice shift, row tiles (needs nx, ny, nz >= R)
+    StepFn shift_rows[3];  // on-lattice shift, row tiles (needs nx, ny, nz >= R): 256 threads,
+                           // 256 threads with non-temporal stores, 512 threads non-temporal
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
     StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
     StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision

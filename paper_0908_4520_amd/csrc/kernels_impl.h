@@ -31,11 +31,13 @@ __device__ __forceinline__ int imod(int v, int n) {
 }
 
 // ---------------------------------------------------------------- exact shift, row tiles
-// Block = `tile` chunks of 256 consecutive cells of one row (y, z).  Thread pulls
+// Block = `tile` chunks of BLOCK consecutive cells of one row (y, z).  Thread pulls
 // f*_a(x - c_a) for every a, collides, and writes f*(x) to the other buffer.  Loads of one
-// population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned.
-template <class L, int N, int S, bool SR>
-__global__ __launch_bounds__(kBlock) void k_shift_rows(StepArgs a) {
+// population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned and,
+// with NTS, non-temporal: the output is not read again in this step, and streaming it past
+// the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
+template <class L, int N, int S, bool SR, int BLOCK, bool NTS>
+__global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_rows(StepArgs a) {
     const size_t ps = a.pstride;
     const T om = (T)a.omega;
     for (uint32_t k = 0; k < a.tile; ++k) {
-        const int x = (int)((xb * a.tile + k) * kBlock + threadIdx.x);
+        const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
         if (x >= nx) break;
         T v[L::Q];
         static_for<L::Q>([&](auto I) {
@@ -71,7 +73,11 @@ __global__ __launch_bounds__(kBlock) void k_shift_rows(StepArgs a) {
         const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            if constexpr (NTS)
+                __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
+            else
+                fout[(size_t)i * ps + o] = r;
         });
     }
 }
@@ -371,9 +377,9 @@ __global__ __launch_bounds__(kBlock) void k_finite(const void *fv, uint32_t ps, 
 // ---------------------------------------------------------------- host launchers
 inline uint32_t blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
 
-template <class L, int N, int S, bool SR>
+template <class L, int N, int S, bool SR, int BLOCK, bool NTS>
 hipError_t launch_shift_rows(const StepArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_shift_rows<L, N, S, SR>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_shift_rows<L, N, S, SR, BLOCK, NTS>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 template <class L, int N, int S, bool SR>
@@ -438,7 +444,9 @@ KernelSet make_set() {
     k.storage = S;
     k.sr = SR ? 1 : 0;
     if constexpr (L::on_lattice) {
-        k.shift_rows = &launch_shift_rows<L, N, S, SR>;
+        k.shift_rows[0] = &launch_shift_rows<L, N, S, SR, 256, false>;
+        k.shift_rows[1] = &launch_shift_rows<L, N, S, SR, 256, true>;
+        k.shift_rows[2] = &launch_shift_rows<L, N, S, SR, 512, true>;
         k.shift_cells = &launch_shift_cells<L, N, S, SR>;
     } else if constexpr (L::D == 2) {
         if constexpr (S == ST_FP64)

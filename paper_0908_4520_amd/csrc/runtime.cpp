@@ -103,8 +103,14 @@ uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-// Step-kernel tile choices: chunks of 256 cells per block (shift) or strip rows (Beam-Warming).
-const int kShiftTiles[] = {1, 2, 4, 8};
+// Step-kernel tile choices.  Shift: kernel variant (0: 256 threads, 1: 256 threads with
+// non-temporal stores, 2: 512 threads with non-temporal stores) and chunks per block.
+// Beam-Warming: rows per strip.
+struct ShiftTile {
+    int variant, block, chunks;
+};
+const ShiftTile kShiftTiles[] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256, 8}, {2, 512, 4},
+                                 {2, 512, 2}, {2, 512, 1}, {1, 256, 4}, {1, 256, 8}};
 const int kBWTiles[] = {16, 32, 8, 4, 64};
 
 }  // namespace
@@ -156,9 +162,10 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
         a.per_row = (nx + kBlock - 1) / kBlock;   // blocks of 4 waves x 64 columns
         a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
     } else if (s->rows_ok) {
-        const uint32_t cpt = (uint32_t)kShiftTiles[tile_index];
+        const ShiftTile &t = kShiftTiles[tile_index];
+        const uint32_t cpt = (uint32_t)t.chunks, blk = (uint32_t)t.block;
         a.tile = cpt;
-        a.per_row = (nx + kBlock * cpt - 1) / (kBlock * cpt);
+        a.per_row = (nx + blk * cpt - 1) / (blk * cpt);
         a.nblocks = a.per_row * (uint32_t)s->g.ny * (uint32_t)s->g.nz;
     } else {
         a.tile = 1;
@@ -172,7 +179,8 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index) 
     const StepArgs a = step_args(s, fin, fout, tile_index);
     if (s->move == LBM_MOVE_BW2)
         return s->o.storage == LBM_FP64 ? s->ks->bw2_f64(a, s->bwd, s->stream) : s->ks->bw2_f32(a, s->bwf, s->stream);
-    return s->rows_ok ? s->ks->shift_rows(a, s->stream) : s->ks->shift_cells(a, s->stream);
+    return s->rows_ok ? s->ks->shift_rows[kShiftTiles[tile_index].variant](a, s->stream)
+                      : s->ks->shift_cells(a, s->stream);
 }
 
 int tile_count(const lbm_sim *s) {
@@ -577,6 +585,19 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t tile) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (tile < 0 || tile >= tile_count(s)) return fail(LBM_EINVAL, "tile %d out of range [0, %d)", tile, tile_count(s));
     s->tile = tile;
+    return LBM_OK;
+}
+
+lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads, int32_t *cells_per_thread,
+                         int64_t *blocks, int32_t *nontemporal) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (tile < 0 || tile >= tile_count(s)) return fail(LBM_EINVAL, "tile %d out of range [0, %d)", tile, tile_count(s));
+    const StepArgs a = step_args(s, s->buf[0], s->buf[1], tile);
+    const bool rows = s->move != LBM_MOVE_BW2 && s->rows_ok;
+    if (block_threads) *block_threads = rows ? kShiftTiles[tile].block : kBlock;
+    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile;
+    if (blocks) *blocks = (int64_t)a.nblocks;
+    if (nontemporal) *nontemporal = rows && kShiftTiles[tile].variant != 0;
     return LBM_OK;
 }
 

@@ -39,7 +39,21 @@ def test_library_loads_and_reports_sizes():
     with lbm.Sim("D2Q37", 4, 3.0, (300, 17, 1), storage="fp32_dev") as s:
         assert (s.ncell, s.Q, s.D) == (300 * 17, 37, 2)
         assert s.bytes_per_step == 2 * 37 * 300 * 17 * 4
-        assert s.tile_count() == 4
+        assert s.tile_count() == 9
+        shapes = [s.tile_info(t) for t in range(9)]
+        assert shapes[0] == {"block": 256, "cells_per_thread": 1, "blocks": 2 * 17, "nontemporal": False}
+        assert {(i["block"], i["nontemporal"]) for i in shapes} == {(256, False), (256, True), (512, True)}
+        for i in shapes:   # every row is covered by whole workgroups, with no workgroup to spare
+            per_row, cover = i["blocks"] // 17, i["block"] * i["cells_per_thread"]
+            assert i["blocks"] % 17 == 0 and per_row * cover >= 300 and (per_row - 1) * cover < 300
+    with lbm.Sim("D2Q16-GH", 3, 3.0, (300, 17, 1), storage="fp32_dev") as s:
+        for t in range(s.tile_count()):
+            i = s.tile_info(t)
+            assert i["block"] == 256 and not i["nontemporal"]
+            # workgroups of 4 x 64 columns, strips of cells_per_thread rows
+            assert i["blocks"] == 2 * -(-17 // i["cells_per_thread"])
+        with pytest.raises(lbm.LbmError):
+            s.tile_info(s.tile_count())
 
 
 def test_d2q9_4x64_fp64_2000_steps():
