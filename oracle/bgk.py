@@ -57,16 +57,22 @@ def lib():
         L.orc_init_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_long,
                                            _dp, _dp, _dp]
         L.orc_step_shift.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _dp, ctypes.c_int, ctypes.c_double,
-                                     ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, _dp]
+                                     ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, _dp, _dp, ctypes.c_int, _dp]
         L.orc_step_bw2.restype = ctypes.c_int
         L.orc_step_bw2.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_double, _dp,
-                                   ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, _dp]
+                                   ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_hermite_tensor.restype = ctypes.c_double
+        L.orc_hermite_tensor.argtypes = [ctypes.c_int, _ip, _dp]
+        L.orc_force_term.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp,
+                                     _dp]
         L.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
         _lib = L
     return _lib
 
 
-def _p(a: np.ndarray):
+def _p(a: np.ndarray | None):
+    if a is None:
+        return None
     assert a.flags["C_CONTIGUOUS"]
     if a.dtype == np.float64:
         return a.ctypes.data_as(_dp)
@@ -171,6 +177,9 @@ class BGK:
             self.nu = courant_numbers(self.vs, cfl)
         self.f = np.zeros((self.vs.Q, self.ncell))
         self.nstep = 0
+        self.force = None          # (amplitude, frequency, wave_axis) of the body force
+        self.last_G = None         # body force times dt of the latest collision, (D, ncell)
+        self.pxw = None            # physical shear stress of the latest collision, (ncell,)
 
     # -- state
     def set_equilibrium(self, rho: np.ndarray, u: np.ndarray):
@@ -179,10 +188,30 @@ class BGK:
         lib().orc_init_equilibrium(self.vs.Q, self.vs.D, _p(self.xi), _p(self.w), self.N, self.ncell,
                                    _p(rho), _p(u), _p(self.f))
         self.nstep = 0
+        self.last_G = None
+        self.pxw = None
 
     def set_shear_wave(self, u0: float, wave_axis: int, rho_noise: float = 0.0, seed: int = 1):
         rho, u = shear_wave_fields(self.grid, u0, wave_axis, rho_noise, seed)
         self.set_equilibrium(rho, u[: self.vs.D])
+
+    # -- body force of the oscillating standing shear wave (Eq. force)
+    def set_force(self, amplitude: float, frequency: float, wave_axis: int):
+        """F_x = amplitude cos(frequency t) cos(2 pi j / N_w), j the cell index along wave_axis,
+        t = n dt the time of the step's collision (the real part of Eq. force with theta y =
+        2 pi j / N_w).  Amplitude and frequency are in the units of Eq. nondime."""
+        self.force = (float(amplitude), float(frequency), int(wave_axis))
+
+    def force_field(self, n: int) -> np.ndarray:
+        """Body force times dt at the collision of step n (time t = n dt), shape (D, ncell)."""
+        amp, freq, ax = self.force
+        n_w = self.grid[ax]
+        dt = time_step(self.vs, n_w, self.cfl)
+        nx, ny, nz = self.grid
+        j = (np.arange(self.ncell) // (nx if ax == 1 else nx * ny)) % n_w
+        G = np.zeros((self.vs.D, self.ncell))
+        G[0] = amp * dt * math.cos(freq * n * dt) * np.cos(2.0 * math.pi * j / n_w)
+        return G
 
     # -- time stepping
     def step(self, n: int = 1):
@@ -190,22 +219,39 @@ class BGK:
         out = np.empty_like(self.f)
         nx, ny, nz = self.grid
         for _ in range(n):
+            G = pxw = None
+            ax = 1
+            if self.force is not None:
+                G = self.force_field(self.nstep + 1)
+                pxw = np.empty(self.ncell)
+                ax = self.force[2]
             if self.mode == "shift":
                 L.orc_step_shift(self.vs.Q, self.vs.D, _p(self.c), _p(self.xi), _p(self.w), self.N,
-                                 self.omega, nx, ny, nz, _p(self.f), _p(out))
+                                 self.omega, nx, ny, nz, _p(self.f), _p(out), _p(G), ax, _p(pxw))
             else:
                 if L.orc_step_bw2(self.vs.Q, self.vs.D, _p(self.xi), _p(self.w), self.N, self.omega,
-                                  _p(self.nu), nx, ny, nz, _p(self.f), _p(out)) != 0:
+                                  _p(self.nu), nx, ny, nz, _p(self.f), _p(out), _p(G), ax, _p(pxw)) != 0:
                     raise MemoryError("oracle scratch allocation failed")
             self.f, out = out, self.f
             self.nstep += 1
+            self.last_G, self.pxw = G, pxw
 
-    # -- observables (the collision conserves rho and rho u, so f* gives the moments at n)
+    # -- observables.  The collision conserves rho and moves rho u by rho G (G = g dt), so f*
+    #    gives the physical moments at n: u = sum_a xi_a f*_a / rho - G/2 (Eq. 2order's rho u).
     def moments(self):
         rho = np.empty(self.ncell)
         u = np.empty((self.vs.D, self.ncell))
         lib().orc_moments(self.vs.Q, self.vs.D, _p(self.xi), self.ncell, _p(self.f), _p(rho), _p(u))
+        if self.last_G is not None:
+            u -= 0.5 * self.last_G
         return rho, u
+
+    def stress_amplitude(self):
+        """(S_s, S_c): sine and cosine projections over the force's wave axis of the physical
+        shear stress sum_a xi_ax xi_aw (f_a - f^eq_a) at the latest collision."""
+        if self.pxw is None:
+            raise RuntimeError("no forced collision since the state was set")
+        return shear_amplitude_of(self.pxw, self.grid, self.force[2])
 
     def shear_amplitude(self, wave_axis: int):
         _, u = self.moments()
@@ -228,6 +274,21 @@ def shear_amplitude_of(ux: np.ndarray, grid, wave_axis: int):
     j = np.arange(n_w)
     k = 2.0 * math.pi / n_w
     return (2.0 / n_w) * float(np.sum(ubar * np.sin(k * j))), (2.0 / n_w) * float(np.sum(ubar * np.cos(k * j)))
+
+
+def oscillation_fit(amp, steps, dt: float, frequency: float, n_first: int, n_last: int) -> complex:
+    """Complex amplitude z of amp(n) ~ Re(z e^{i frequency n dt}) by least squares over
+    n_first <= n <= n_last (for frequency 0: the mean).  The phase lag behind a force
+    proportional to cos(frequency t) is -arg z."""
+    amp = np.asarray(amp, dtype=np.float64)
+    steps = np.asarray(steps, dtype=np.float64)
+    sel = (steps >= n_first) & (steps <= n_last)
+    t = steps[sel] * dt
+    if frequency == 0.0:
+        return complex(float(np.mean(amp[sel])), 0.0)
+    A = np.stack([np.cos(frequency * t), np.sin(frequency * t)], axis=1)
+    (a, b), *_ = np.linalg.lstsq(A, amp[sel], rcond=None)
+    return complex(a, -b)
 
 
 def decay_rate(amp: np.ndarray, steps: np.ndarray, n_first: int, n_last: int) -> float:

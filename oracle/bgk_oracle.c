@@ -20,6 +20,16 @@
  *      truncated after order N, s = xi_a.u, q = u.u         (Eqs. approxf, an, demoeq)
  *   4. relax:    f*_a = f_a - omega (f_a - f^eq_a),  omega = dt/(Kn + dt/2)  (Eq. 2order)
  *
+ * With a body force g (section 2.1, force expansion; Eq. 2order with its forcing term) the
+ * moved populations are the shifted variable f~ of Eq. 2order, and
+ *   2'. rho u = sum_a xi_a f~_a + rho G/2,           G = g dt
+ *   4'. f*_a = f~_a - omega (f~_a - f^eq_a) + (1 - omega/2) F_a,
+ *       F_a = w_a sum_{n=1..N} 1/(n-1)! (G a^(n-1)) : chi^(n)(xi_a)   (force term times dt)
+ * since Kn dt/(Kn + dt/2) = (1 - omega/2) dt.  The expansion coefficients in F are those of
+ * the equilibrium, a^(m) = rho u^{(x)m}, with the u of step 2'.  The physical distribution
+ * behind f~ is f = f^eq + (1 - omega/2) (f~ - f^eq + F/2) (the inverse of the definition of
+ * f~ in section 2.2), whose second moment gives the shear stress.
+ *
  * Arrays are structure-of-arrays: f[a * ncell + cell], cell = x + nx*(y + ny*z).
  * Periodic in every direction.
  */
@@ -59,17 +69,82 @@ void orc_equilibrium(int Q, int D, const double *xi, const double *w, int N,
     }
 }
 
-/* Collide one cell in place: f[a] holds the moved populations on entry, f* on exit. */
-static void collide(int Q, int D, const double *xi, const double *w, int N, double omega, double *f)
+/* One component chi^(n)_{i_1..i_n}(xi) of the tensor Hermite polynomial of order n <= 4,
+ * (-1)^n e^{xi^2/2} times the n-th derivative of e^{-xi^2/2} (Eq. approxf), written out:
+ *   n = 1: xi_i
+ *   n = 2: xi_i xi_j - d_ij
+ *   n = 3: xi_i xi_j xi_k - (xi_i d_jk + xi_j d_ik + xi_k d_ij)
+ *   n = 4: xi_i xi_j xi_k xi_l - (xi_i xi_j d_kl + xi_i xi_k d_jl + xi_i xi_l d_jk
+ *          + xi_j xi_k d_il + xi_j xi_l d_ik + xi_k xi_l d_ij) + d_ij d_kl + d_ik d_jl + d_il d_jk */
+double orc_hermite_tensor(int n, const int *id, const double *x)
 {
-    double rho = 0.0, j[ORC_MAXD] = {0.0, 0.0, 0.0}, u[ORC_MAXD], feq[ORC_MAXQ];
+#define DL(p, q) (id[p] == id[q] ? 1.0 : 0.0)
+#define X(p) (x[id[p]])
+    switch (n) {
+    case 0: return 1.0;
+    case 1: return X(0);
+    case 2: return X(0) * X(1) - DL(0, 1);
+    case 3: return X(0) * X(1) * X(2) - (X(0) * DL(1, 2) + X(1) * DL(0, 2) + X(2) * DL(0, 1));
+    case 4:
+        return X(0) * X(1) * X(2) * X(3)
+             - (X(0) * X(1) * DL(2, 3) + X(0) * X(2) * DL(1, 3) + X(0) * X(3) * DL(1, 2)
+                + X(1) * X(2) * DL(0, 3) + X(1) * X(3) * DL(0, 2) + X(2) * X(3) * DL(0, 1))
+             + DL(0, 1) * DL(2, 3) + DL(0, 2) * DL(1, 3) + DL(0, 3) * DL(1, 2);
+    default: return 0.0;
+    }
+#undef DL
+#undef X
+}
+
+/* Force term times dt for every a (section 2.1, force expansion):
+ *   F_a = w_a sum_{n=1..N} 1/(n-1)! sum_{i, j_1..j_{n-1}} G_i rho u_j1 .. u_j(n-1) chi^(n)_{i j_1..j_{n-1}}(xi_a)
+ * summed over every index tuple in {0..D-1}^n. */
+void orc_force_term(int Q, int D, const double *xi, const double *w, int N, double rho, const double *u,
+                    const double *G, double *F)
+{
+    for (int a = 0; a < Q; ++a) {
+        double sum = 0.0, fact = 1.0;    /* fact = (n-1)! */
+        for (int n = 1; n <= N; ++n) {
+            if (n > 1) fact *= (double)(n - 1);
+            long count = 1;
+            for (int k = 0; k < n; ++k) count *= D;
+            for (long t = 0; t < count; ++t) {
+                int id[4];
+                long r = t;
+                for (int k = 0; k < n; ++k) { id[k] = (int)(r % D); r /= D; }
+                double coef = G[id[0]] * rho;
+                for (int k = 1; k < n; ++k) coef *= u[id[k]];
+                sum += coef * orc_hermite_tensor(n, id, xi + a * D) / fact;
+            }
+        }
+        F[a] = w[a] * sum;
+    }
+}
+
+/* Collide one cell in place: f[a] holds the moved populations on entry, f* on exit.
+ * G (length D, may be NULL) is the body force times dt at this cell; if pxw is not NULL it
+ * receives the physical shear stress sum_a xi_a0 xi_aw (f_a - f^eq_a) with w = wave_axis. */
+static void collide(int Q, int D, const double *xi, const double *w, int N, double omega, const double *G,
+                    int wave_axis, double *pxw, double *f)
+{
+    double rho = 0.0, j[ORC_MAXD] = {0.0, 0.0, 0.0}, u[ORC_MAXD], feq[ORC_MAXQ], F[ORC_MAXQ];
     for (int a = 0; a < Q; ++a) {
         rho += f[a];
         for (int d = 0; d < D; ++d) j[d] += xi[a * D + d] * f[a];
     }
-    for (int d = 0; d < D; ++d) u[d] = j[d] / rho;
+    for (int d = 0; d < D; ++d) u[d] = j[d] / rho + (G ? 0.5 * G[d] : 0.0);
     orc_equilibrium(Q, D, xi, w, N, rho, u, feq);
-    for (int a = 0; a < Q; ++a) f[a] = f[a] - omega * (f[a] - feq[a]);
+    if (G)
+        orc_force_term(Q, D, xi, w, N, rho, u, G, F);
+    else
+        for (int a = 0; a < Q; ++a) F[a] = 0.0;
+    if (pxw) {
+        double p = 0.0;
+        for (int a = 0; a < Q; ++a)
+            p += xi[a * D + 0] * xi[a * D + wave_axis] * (1.0 - 0.5 * omega) * (f[a] - feq[a] + 0.5 * F[a]);
+        *pxw = p;
+    }
+    for (int a = 0; a < Q; ++a) f[a] = f[a] - omega * (f[a] - feq[a]) + (1.0 - 0.5 * omega) * F[a];
 }
 
 /* Equilibrium initial state from per-cell rho[cell] and u[d * ncell + cell]. */
@@ -85,9 +160,12 @@ void orc_init_equilibrium(int Q, int D, const double *xi, const double *w, int N
     }
 }
 
-/* One step with the exact on-lattice shift: c[a * D + d] are integer displacements. */
+/* One step with the exact on-lattice shift: c[a * D + d] are integer displacements.
+ * G[d * ncell + cell] (may be NULL) is the body force times dt of this step's collision;
+ * pxw[cell] (may be NULL) receives the physical shear stress along (x, wave_axis). */
 void orc_step_shift(int Q, int D, const int *c, const double *xi, const double *w, int N,
-                    double omega, long nx, long ny, long nz, const double *fin, double *fout)
+                    double omega, long nx, long ny, long nz, const double *fin, double *fout,
+                    const double *G, int wave_axis, double *pxw)
 {
     const long ncell = nx * ny * nz;
 #pragma omp parallel for collapse(2) schedule(static)
@@ -101,8 +179,11 @@ void orc_step_shift(int Q, int D, const int *c, const double *xi, const double *
                     long sz = D == 3 ? imod(z - c[a * D + 2], nz) : z;
                     f[a] = fin[a * ncell + sx + nx * (sy + ny * sz)];
                 }
-                collide(Q, D, xi, w, N, omega, f);
-                for (int a = 0; a < Q; ++a) fout[a * ncell + x + nx * (y + ny * z)] = f[a];
+                const long cell = x + nx * (y + ny * z);
+                double g[ORC_MAXD];
+                for (int d = 0; d < D; ++d) g[d] = G ? G[d * ncell + cell] : 0.0;
+                collide(Q, D, xi, w, N, omega, G ? g : NULL, wave_axis, pxw ? pxw + cell : NULL, f);
+                for (int a = 0; a < Q; ++a) fout[a * ncell + cell] = f[a];
             }
 }
 
@@ -132,10 +213,11 @@ static void bw_axis(double nu, int axis, long nx, long ny, long nz, const double
 }
 
 /* One step of the discrete velocity method: advect every population along x, then y
- * (then z) with Courant numbers nu[a * D + d] = xi_ad dt/dx, then collide.
- * Returns 0, or -1 if scratch memory could not be allocated. */
+ * (then z) with Courant numbers nu[a * D + d] = xi_ad dt/dx, then collide (G, wave_axis and
+ * pxw as for the shift).  Returns 0, or -1 if scratch memory could not be allocated. */
 int orc_step_bw2(int Q, int D, const double *xi, const double *w, int N, double omega,
-                 const double *nu, long nx, long ny, long nz, const double *fin, double *fout)
+                 const double *nu, long nx, long ny, long nz, const double *fin, double *fout,
+                 const double *G, int wave_axis, double *pxw)
 {
     const long ncell = nx * ny * nz;
     double *p0 = malloc(sizeof(double) * ncell), *p1 = malloc(sizeof(double) * ncell);
@@ -155,9 +237,10 @@ int orc_step_bw2(int Q, int D, const double *xi, const double *w, int N, double 
     free(p1);
 #pragma omp parallel for schedule(static)
     for (long cell = 0; cell < ncell; ++cell) {
-        double f[ORC_MAXQ];
+        double f[ORC_MAXQ], g[ORC_MAXD];
         for (int a = 0; a < Q; ++a) f[a] = fout[a * ncell + cell];
-        collide(Q, D, xi, w, N, omega, f);
+        for (int d = 0; d < D; ++d) g[d] = G ? G[d * ncell + cell] : 0.0;
+        collide(Q, D, xi, w, N, omega, G ? g : NULL, wave_axis, pxw ? pxw + cell : NULL, f);
         for (int a = 0; a < Q; ++a) fout[a * ncell + cell] = f[a];
     }
     return 0;

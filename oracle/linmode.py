@@ -79,3 +79,56 @@ def shear_decay_per_step(vs, omega, n_w, wave_axis, mode, cfl=0.5):
     coef = np.linalg.solve(V, f0)
     weight = np.abs(coef * (vs.xi[:, 0] @ V))
     return float(-math.log(abs(ev[int(np.argmax(weight))])))
+
+
+# ------------------------------------------------------------------ forced standing shear wave
+# With the body force F_x = A cos(phi t) cos(k y) of Eq. force, linearised about f_a = w_a and
+# written as delta f_a = Re(fhat_a e^{i k j}), one step of Eq. 2order is
+#     fhat(n+1) = M fhat(n) + b cos(phi t_{n+1}),   b_a = w_a xi_ax G0,  G0 = A dt,
+# because the equilibrium's velocity carries +G/2 (relaxed with weight omega) and the force
+# term enters with 1 - omega/2: omega/2 + 1 - omega/2 = 1.  The physical velocity at t_n is
+# xi_x . fhat(n) - G0 cos(phi t_n)/2 (no force before the first step), and the shear stress of
+# the collision at t_n is (1 - omega/2) sum_a xi_ax xi_aw (S fhat(n-1))_a (the equilibrium and
+# force parts of f - f^eq have no linear xw moment).  Projections: A_c = Re, A_s = -Im.
+
+def _forced_parts(vs, omega, n_w, wave_axis, mode, G0, cfl):
+    M = step_matrix(vs, omega, n_w, wave_axis, mode, cfl)
+    S = move_factors(vs, n_w, wave_axis, mode, cfl)
+    b = (vs.w * vs.xi[:, 0] * G0).astype(np.complex128)
+    v = vs.xi[:, 0] * vs.xi[:, wave_axis] * S
+    return M, b, v
+
+
+def forced_series(vs, omega, n_w, wave_axis, mode, steps, G0, phi_dt, cfl=0.5):
+    """Velocity (A_s, A_c) and stress (S_s, S_c) projections for n = 0..steps from rest.
+    Rows of the returned (steps+1, 4) array; the stress of n = 0 is 0 (no collision yet)."""
+    M, b, v = _forced_parts(vs, omega, n_w, wave_axis, mode, G0, cfl)
+    f = np.zeros(vs.Q, dtype=np.complex128)
+    out = np.zeros((steps + 1, 4))
+    for n in range(steps + 1):
+        u = vs.xi[:, 0] @ f - (0.5 * G0 * math.cos(phi_dt * n) if n > 0 else 0.0)
+        out[n, 0], out[n, 1] = -u.imag, u.real
+        fn = M @ f + b * math.cos(phi_dt * (n + 1))
+        if n < steps:
+            s = (1.0 - 0.5 * omega) * (v @ f)
+            out[n + 1, 2], out[n + 1, 3] = -s.imag, s.real
+        f = fn
+    return out
+
+
+def forced_response(vs, omega, n_w, wave_axis, mode, G0, phi_dt, cfl=0.5):
+    """Complex amplitudes of the periodic state: each projection P(n) = Re(z e^{i phi_dt n}).
+    Returns (velocity sine, velocity cosine, stress sine, stress cosine) amplitudes."""
+    M, b, v = _forced_parts(vs, omega, n_w, wave_axis, mode, G0, cfl)
+    I = np.eye(vs.Q)
+    e = np.exp(1j * phi_dt)
+    Xp = np.linalg.solve(e * I - M, 0.5 * b * e)
+    Xm = np.linalg.solve(np.conj(e) * I - M, 0.5 * b * np.conj(e))
+    zp, zm = vs.xi[:, 0] @ Xp, vs.xi[:, 0] @ Xm
+    u_c = zp + np.conj(zm) - 0.5 * G0
+    u_s = 1j * zp - 1j * np.conj(zm)
+    k = 1.0 - 0.5 * omega
+    sp, sm = k * (v @ Xp) / e, k * (v @ Xm) * e
+    s_c = sp + np.conj(sm)
+    s_s = 1j * sp - 1j * np.conj(sm)
+    return complex(u_s), complex(u_c), complex(s_s), complex(s_c)
