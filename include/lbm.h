@@ -110,6 +110,9 @@ lbm_status lbm_lattice_info(lbm_lattice lat, int32_t *Q, int32_t *D, int32_t *c,
  * on-lattice sets (xi_a dt = c_a dx) and dt = cfl dx / max|xi| for advection.
  * Returns tau = Kn/dt + 1/2, or NaN for invalid arguments. */
 double lbm_tau_from_kn(lbm_lattice lat, lbm_move move, double kn, int32_t wavelength_cells, double cfl);
+/* The non-dimensional time step dt of one step in the same units (dt = dx / scale, or
+ * cfl dx / max|xi| for advection); NaN for invalid arguments. */
+double lbm_time_step(lbm_lattice lat, lbm_move move, int32_t wavelength_cells, double cfl);
 
 /* Create a simulation with the default options.  eq_order N in 1..4; tau > 1/2 (INFINITY
  * means collisionless, omega = 0); every grid dimension >= 1; nz = 1 for 2-D sets.
@@ -141,8 +144,31 @@ lbm_status lbm_step(lbm_sim *s, int64_t n);
 /* Number of steps taken since the last set call. */
 int64_t lbm_step_count(const lbm_sim *s);
 
+/* Body force of the oscillating standing shear wave (section 4, Eq. force, real part):
+ * F_x = amplitude cos(frequency t) cos(2 pi j / N_w), j the cell index along wave_axis
+ * (1 = y, 2 = z for 3-D on-lattice sets; 1 for advection) and N_w that axis' length, with
+ * amplitude and frequency in the units of Eq. nondime and t = n dt (lbm_time_step for N_w)
+ * the time of step n's collision.  From the next step on, every step uses the forced kernels
+ * of the second-order scheme (Eq. 2order with its force term; the Hermite force term of
+ * section 2.1 at order eq_order, expanded with the equilibrium's coefficients rho u^n).  The
+ * stored state is then the shifted variable of Eq. 2order: lbm_moments, lbm_shear_amplitude
+ * and lbm_totals report the physical velocity rho u = sum_a xi_a f*_a - rho G/2 (G the force
+ * times dt of the latest collision, none at step 0).  amplitude 0 keeps the forced kernels
+ * (and the stress below); wave_axis 0 switches back to the unforced kernels.  The row-tiled
+ * forced kernel has 4 tiles (the 256-thread plain-store ones).  Allocates two small device
+ * tables.  LBM_EINVAL for an invalid axis or non-finite values. */
+lbm_status lbm_set_force(lbm_sim *s, double amplitude, double frequency, int32_t wave_axis);
+
+/* Sine and cosine projections over the force's wave axis (as lbm_shear_amplitude) of the
+ * physical shear stress sum_a xi_ax xi_aw (f_a - f^eq_a), w the wave axis, at the collision of
+ * the latest step, where f = f^eq + (1 - omega/2)(f~ - f^eq + F/2) is the distribution behind
+ * the stored variable f~ (the inverse of its definition in section 2.2).  Summed in FP64 in a
+ * fixed order.  LBM_ESTATE if no forced step ran since lbm_set_force or a set call. */
+lbm_status lbm_shear_stress_amplitude(lbm_sim *s, double *s_sin, double *s_cos);
+
 /* Host copies (synchronising): rho[ncell] and u[D*ncell] in FP64 from the stored f*
- * (the collision conserves rho and rho u, so these are the moments at the current step). */
+ * (the collision conserves rho and rho u, so these are the moments at the current step;
+ * with a body force, u is the physical velocity described at lbm_set_force). */
 lbm_status lbm_moments(lbm_sim *s, double *rho, double *u);
 
 /* Sine and cosine projections of the x-velocity along wave_axis, in FP64:
@@ -171,6 +197,14 @@ lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes);
  * in FP64 (the decay rate per step of the shear-wave amplitude).  Needs >= 2 points. */
 lbm_status lbm_fit_decay(const double *amp, const int64_t *steps, int64_t count, int64_t n_first,
                          int64_t n_last, double *gamma);
+
+/* Complex amplitude z = re + i im of a periodic response amp[k] = Re(z e^{i frequency t_k}),
+ * t_k = steps[k] dt, by least squares over n_first <= steps[k] <= n_last (for frequency 0:
+ * the mean, im = 0).  Against a force proportional to cos(frequency t) the amplitude is |z|
+ * and the phase lag -arg z.  LBM_EINVAL for NULL pointers, dt <= 0, an empty window or one
+ * that does not resolve the oscillation. */
+lbm_status lbm_fit_oscillation(const double *amp, const int64_t *steps, int64_t count, double dt, double frequency,
+                               int64_t n_first, int64_t n_last, double *re, double *im);
 
 /* Tile choices of the step kernel for this simulation's configuration; lbm_set_tile picks one
  * (0 = default), lbm_autotune times every choice on a scratch copy of the state and keeps the

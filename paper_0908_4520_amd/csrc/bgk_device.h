@@ -30,6 +30,19 @@
 // v^eq - v (small, so finely resolved), not to v^eq or its coefficients.
 // With omega = 0 every term added to v_a is an exact zero, so a collisionless step moves
 // the stored values bit for bit.
+//
+// Body force (section 2.1, force expansion; Eq. 2order with its forcing term).  The stored
+// populations are then the shifted variable f~ of Eq. 2order; with G = g dt (here along x)
+//   rho u = j + rho G/2,
+//   f*_a = f~_a - omega (f~_a - f^eq_a) + (1 - omega/2) F_a,
+// (Kn dt/(Kn + dt/2) = (1 - omega/2) dt), and the force term of order N, with the expansion
+// coefficients of the equilibrium a^(m) = rho u^{(x)m}, is the derivative of the equilibrium
+// along G at fixed rho:
+//   F_a = w_a rho [(xi_a.G) P_{N-1}(s_a) - (u.G) P_{N-2}(s_a)],   P_{-1} = 0,
+// because d/du of u^{(x)n}:chi^(n)/n! is the n-1 term contracted with chi^(n), and in the
+// (s, q) form dP_N/ds = P_{N-1}, dP_N/dq = -P_{N-2}/2.  The physical distribution behind f~
+// is f = f^eq + (1 - omega/2)(f~ - f^eq + F/2) (inverting the definition of f~), whose
+// xy (xz) moment is the shear stress the forced kernels can also sum.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -185,16 +198,20 @@ constexpr double rounded_momentum_sum() {   // sum_a w_a xi_ax^2 (the same for e
     return s;
 }
 
-// Relax the Q values in place; omega = 1/tau (0 = collisionless).
-template <class L, int N, int S, class T>
-__device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
+// Relax the Q values in place; omega = 1/tau (0 = collisionless).  With FORCED, Gx is the
+// body force times dt at this cell and sigma receives the physical shear stresses
+// sum_a xi_ax xi_ay (f_a - f^eq_a) and, in 3-D, sum_a xi_ax xi_az (f_a - f^eq_a).
+template <class L, int N, int S, class T, bool FORCED>
+__device__ __forceinline__ void collide_impl(T (&v)[L::Q], T omega, T Gx, T (&sigma)[2]) {
     static_assert(N >= 1 && N <= 4, "Hermite order 1..4");
     constexpr double delta0 = 1.0 / rounded_mass_sum<L, T>() - 1.0;
     constexpr double delta1 = 1.0 / rounded_momentum_sum<L, T>() - 1.0;
     const Moments<T> m = project<L, S>(v);
     const T rho = Codec<S>::dev ? T(1) + m.d : m.d;
     const T inv = T(1) / rho;
-    const T ux = m.jx * inv, uy = m.jy * inv, uz = (L::D == 3) ? m.jz * inv : T(0);
+    T ux = m.jx * inv;
+    if constexpr (FORCED) ux += T(0.5) * Gx;
+    const T uy = m.jy * inv, uz = (L::D == 3) ? m.jz * inv : T(0);
     const T q = ux * ux + uy * uy + uz * uz;
     // P_N(s) - 1 = a0m + a1 s + a2 s^2 + a3 s^3 + a4 s^4
     T a0m = T(0), a1 = T(1), a2 = T(0);
@@ -207,6 +224,11 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
     const T C2 = rho * a2;
     const T C3 = rho * T(1.0 / 6.0);
     const T C4 = rho * T(1.0 / 24.0);
+    // force: F_a / e_a = rG xi_ax P_{N-1}(s) - rGu P_{N-2}(s), with
+    // P_0 = 1, P_1 = 1 + s, P_2 = b0 + s + s^2/2, P_3 = b0 + b0 s + s^2/2 + s^3/6, b0 = 1 - q/2
+    const T rG = rho * Gx, rGu = rho * Gx * ux, b0 = T(1) - T(0.5) * q;
+    const T kf = T(1) - T(0.5) * omega;
+    T sxy = T(0), sxz = T(0);
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
         T s = T(0);
@@ -226,8 +248,38 @@ __device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
             neq = (p - v[a]) + corr;
         else
             neq = (T(ef) * p - v[a]) + T(ef) * corr;
-        v[a] = v[a] + omega * neq;
+        if constexpr (FORCED) {
+            T pm1, pm2;                             // P_{N-1}(s), P_{N-2}(s)
+            if constexpr (N == 1) { pm1 = T(1); pm2 = T(0); }
+            if constexpr (N == 2) { pm1 = T(1) + s; pm2 = T(1); }
+            if constexpr (N == 3) { pm1 = b0 + s * (T(1) + s * T(0.5)); pm2 = T(1) + s; }
+            if constexpr (N == 4) {
+                pm1 = b0 + s * (b0 + s * (T(0.5) + s * T(1.0 / 6.0)));
+                pm2 = b0 + s * (T(1) + s * T(0.5));
+            }
+            T fa = -(rGu * pm2);
+            if constexpr (L::xi[a][0] != 0.0) fa += T(L::xi[a][0]) * rG * pm1;
+            if constexpr (ef != 1.0) fa *= T(ef);
+            // f_a - f^eq_a = m_a (v_a - v^eq_a) in v-space units
+            constexpr double mxy = moment_factor<L, S, a>() * L::xi[a][0] * L::xi[a][1];
+            constexpr double mxz = moment_factor<L, S, a>() * L::xi[a][0] * L::xi[a][2];
+            if constexpr (mxy != 0.0) sxy += T(mxy) * (T(0.5) * fa - neq);
+            if constexpr (L::D == 3 && mxz != 0.0) sxz += T(mxz) * (T(0.5) * fa - neq);
+            v[a] = v[a] + omega * neq + kf * fa;
+        } else {
+            v[a] = v[a] + omega * neq;
+        }
     });
+    if constexpr (FORCED) {
+        sigma[0] = kf * sxy;
+        sigma[1] = kf * sxz;
+    }
+}
+
+template <class L, int N, int S, class T>
+__device__ __forceinline__ void collide(T (&v)[L::Q], T omega) {
+    T unused[2];
+    collide_impl<L, N, S, T, false>(v, omega, T(0), unused);
 }
 
 // ------------------------------------------------------------------ equilibrium (init)

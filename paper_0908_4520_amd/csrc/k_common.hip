@@ -8,17 +8,19 @@ std::vector<KernelSet> &registry() {
     return r;
 }
 
-// One block of 64 threads: thread k < 6 adds partials[b][k] for b = 0..nblocks-1 in order.
-__global__ __launch_bounds__(64) void k_diag_final(const double *partials, uint32_t nblocks, double *out) {
+// One block of 64 threads: thread k < width adds partials[b][k] for b = 0..nblocks-1 in order.
+__global__ __launch_bounds__(64) void k_diag_final(const double *partials, uint32_t nblocks, int width,
+                                                   double *out) {
     const int k = threadIdx.x;
-    if (k >= 6) return;
+    if (k >= width) return;
     double s = 0.0;
-    for (uint32_t b = 0; b < nblocks; ++b) s += partials[(size_t)b * 6 + k];
+    for (uint32_t b = 0; b < nblocks; ++b) s += partials[(size_t)b * width + k];
     out[k] = s;
 }
 
-hipError_t diag_final(const double *partials, uint32_t nblocks, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partials, nblocks, out);
+hipError_t diag_final(const double *partials, uint32_t nblocks, int width, double *out, hipStream_t s) {
+    if (width < 1 || width > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partials, nblocks, width, out);
     return hipGetLastError();
 }
 

@@ -26,6 +26,14 @@ struct StepArgs {
     uint32_t nblocks;      // grid size (1-D)
     uint32_t sr_key;       // per-step key of the stochastic-rounding stream
     double omega;          // 1/tau (0 = collisionless)
+    // Body force of the standing shear wave, read by the forced kernels only:
+    // G_x(cell) = force_g * force_cos[j], j the cell's index along force_axis.
+    double force_g;            // force times dt at this step's collision time
+    const double *force_cos;   // cos(2 pi j / N_w) along the force axis
+    const double *force_sin;   // sin(2 pi j / N_w), weights of the stress projection
+    double *stress;            // per-wave sums [nblocks * waves per block][2] of the shear stress
+                               // times sin and cos, or null
+    int32_t force_axis;        // 1 (y) or 2 (z)
 };
 
 // Beam-Warming coefficients per population and axis: g = f - alpha D1 + beta D2 with
@@ -53,6 +61,11 @@ struct DiagArgs {
     int32_t wave_axis;
     const double *sin_tab, *cos_tab;
     double *partials;        // [nblocks][6]: sum u_x sin, sum u_x cos, sum d, sum j_x, j_y, j_z
+    // Half the force times dt of the latest collision (0 if none): the velocity is
+    // sum_a xi_a f*_a / rho - G/2 with G_x = 2 half_g force_cos[j] (j along force_axis).
+    double half_g;
+    const double *force_cos;
+    int32_t force_axis;
 };
 
 using StepFn = hipError_t (*)(const StepArgs &, hipStream_t);
@@ -65,8 +78,7 @@ using DecodeFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell,
                                 double mul, double *out, hipStream_t);
 using EncodeFn = hipError_t (*)(void *f, uint32_t pstride, uint32_t ncell, int a, double add,
                                 double scale, const double *in, uint32_t sr_key, hipStream_t);
-using MomentsFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, double *rho,
-                                 double *u, hipStream_t);
+using MomentsFn = hipError_t (*)(const DiagArgs &, double *rho, double *u, hipStream_t);
 using DiagFn = hipError_t (*)(const DiagArgs &, uint32_t nblocks, hipStream_t);
 using FiniteFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, int Q, int *flag,
                                 hipStream_t);
@@ -79,6 +91,11 @@ struct KernelSet {
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
     StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
     StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision
+    // The same with the body force (256 threads, plain stores for the row tiles)
+    StepFn shift_rows_forced;
+    StepFn shift_cells_forced;
+    StepBW32 bw2_f32_forced;
+    StepBW64 bw2_f64_forced;
     WaveFn init_wave;
     FieldsFn init_fields;
     DecodeFn decode;
@@ -103,7 +120,8 @@ void register_D2Q25_CK();
 // Zero n ints with a kernel (kept out of hipMemsetAsync so the step path can be captured).
 hipError_t fill_zero(int *p, uint32_t n, hipStream_t s);
 
-// Fixed-order final reduction of DiagFn partials: out[k] = sum_b partials[b][k], k < 6.
-hipError_t diag_final(const double *partials, uint32_t nblocks, double *out, hipStream_t s);
+// Fixed-order final reduction of per-block partial sums: out[k] = sum_b partials[b][k],
+// k < width <= 8 (width 6 for DiagFn partials, 2 for the stress sums of the forced steps).
+hipError_t diag_final(const double *partials, uint32_t nblocks, int width, double *out, hipStream_t s);
 
 }  // namespace lbm

@@ -30,13 +30,34 @@ __device__ __forceinline__ int imod(int v, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Sum over the 64 lanes of a wave in a fixed butterfly order (every lane gets the sum).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Forced steps: lane 0 of each wave stores the wave's sums of stress x sin and stress x cos
+// in slot blockIdx.x * (BLOCK / 64) + wave; the slots are added in index order afterwards.
+template <int BLOCK>
+__device__ __forceinline__ void store_stress(double *out, double ss, double sc) {
+    ss = wave_sum(ss);
+    sc = wave_sum(sc);
+    if ((threadIdx.x & 63) == 0) {
+        const size_t slot = (size_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+        out[2 * slot] = ss;
+        out[2 * slot + 1] = sc;
+    }
+}
+
 // ---------------------------------------------------------------- exact shift, row tiles
 // Block = `tile` chunks of BLOCK consecutive cells of one row (y, z).  Thread pulls
 // f*_a(x - c_a) for every a, collides, and writes f*(x) to the other buffer.  Loads of one
 // population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned and,
 // with NTS, non-temporal: the output is not read again in this step, and streaming it past
 // the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
-template <class L, int N, int S, bool SR, int BLOCK, bool NTS>
+// With F the collision adds the body force of the row and the stress sums are stored.
+template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
 __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
     using C = Codec<S>;
     using raw = typename C::raw;
@@ -50,6 +71,10 @@ __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
     raw *__restrict__ fout = static_cast<raw *>(a.fout);
     const size_t ps = a.pstride;
     const T om = (T)a.omega;
+    const int jf = a.force_axis == 1 ? y : z;           // row index along the force axis
+    T Gx = T(0);
+    if constexpr (F) Gx = (T)(a.force_g * a.force_cos[jf]);
+    double sig_sum = 0.0;
     for (uint32_t k = 0; k < a.tile; ++k) {
         const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
         if (x >= nx) break;
@@ -68,7 +93,13 @@ __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
             const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * (size_t)nx;
             v[i] = C::dec(p[xs]);
         });
-        collide<L, N, S, T>(v, om);
+        if constexpr (F) {
+            T sig[2];
+            collide_impl<L, N, S, T, true>(v, om, Gx, sig);
+            sig_sum += (double)(a.force_axis == 1 ? sig[0] : sig[1]);
+        } else {
+            collide<L, N, S, T>(v, om);
+        }
         const size_t o = (size_t)row * (size_t)nx + (size_t)x;
         const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
         static_for<L::Q>([&](auto I) {
@@ -80,36 +111,51 @@ __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
                 fout[(size_t)i * ps + o] = r;
         });
     }
+    if constexpr (F)
+        if (a.stress) store_stress<BLOCK>(a.stress, sig_sum * a.force_sin[jf], sig_sum * a.force_cos[jf]);
 }
 
 // ---------------------------------------------------------------- exact shift, any grid
-template <class L, int N, int S, bool SR>
+template <class L, int N, int S, bool SR, bool F>
 __global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;
     const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
-    if (cell >= ncell) return;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int x = (int)(cell % (uint32_t)nx);
-    const uint32_t t = cell / (uint32_t)nx;
-    const int y = (int)(t % (uint32_t)ny), z = (int)(t / (uint32_t)ny);
-    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
-    raw *__restrict__ fout = static_cast<raw *>(a.fout);
-    const size_t ps = a.pstride;
-    T v[L::Q];
-    static_for<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny), zs = imod(z - L::c[i][2], nz);
-        v[i] = C::dec(fin[(size_t)i * ps + (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs)]);
-    });
-    collide<L, N, S, T>(v, (T)a.omega);
-    const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
-    static_for<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        fout[(size_t)i * ps + cell] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
-    });
+    double ss = 0.0, sc = 0.0;
+    if (cell < ncell) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(cell % (uint32_t)nx);
+        const uint32_t t = cell / (uint32_t)nx;
+        const int y = (int)(t % (uint32_t)ny), z = (int)(t / (uint32_t)ny);
+        const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+        raw *__restrict__ fout = static_cast<raw *>(a.fout);
+        const size_t ps = a.pstride;
+        T v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny), zs = imod(z - L::c[i][2], nz);
+            v[i] = C::dec(fin[(size_t)i * ps + (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs)]);
+        });
+        if constexpr (F) {
+            const int jf = a.force_axis == 1 ? y : z;
+            T sig[2];
+            collide_impl<L, N, S, T, true>(v, (T)a.omega, (T)(a.force_g * a.force_cos[jf]), sig);
+            const double sg = (double)(a.force_axis == 1 ? sig[0] : sig[1]);
+            ss = sg * a.force_sin[jf];
+            sc = sg * a.force_cos[jf];
+        } else {
+            collide<L, N, S, T>(v, (T)a.omega);
+        }
+        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fout[(size_t)i * ps + cell] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+        });
+    }
+    if constexpr (F)
+        if (a.stress) store_stress<kBlock>(a.stress, ss, sc);
 }
 
 // ---------------------------------------------------------------- Beam-Warming, 2-D
@@ -141,7 +187,8 @@ __device__ __forceinline__ double dpp_shl(double old, double v) {
 // one extra load per population-row that touches a single cache line and enter the shift as
 // the value of the vacated lane.  So every population-row costs one aligned load, one
 // one-line halo load and three lane shifts; stores are whole aligned wave segments.
-template <class L, int N, int S, bool SR, class T>
+// With F the collision adds the body force (force axis y) and the stress sums are stored.
+template <class L, int N, int S, bool SR, class T, bool F>
 __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
     using C = Codec<S>;
@@ -152,7 +199,11 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     const int nx = a.nx, ny = a.ny;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x0 = (int)(xb * (kBlock / 64) + wv) * 64;
-    if (x0 >= nx) return;                              // whole wave leaves together
+    if (x0 >= nx) {                                    // whole wave leaves together
+        if constexpr (F)
+            if (a.stress) store_stress<kBlock>(a.stress, 0.0, 0.0);
+        return;
+    }
     const int xo = x0 + lane;                          // this lane's column (may exceed nx)
     const int xl = xo % nx;                            // column it loads (wrapped)
     const int hl = (x0 - 1 - (lane == 1 ? 1 : 0) + 2 * nx) % nx;   // lane 0: x0-1, lane 1: x0-2
@@ -195,6 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
         });
     }
     const T om = (T)a.omega;
+    double ss = 0.0, sc = 0.0;
     for (int y = y0; y < y1; ++y) {
         T v[L::Q];
         const size_t r0 = row_of(y), rp2 = row_of(y + 2);
@@ -212,7 +264,16 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
                 B[i] = Cn;
             }
         });
-        collide<L, N, S, T>(v, om);
+        if constexpr (F) {
+            T sig[2];
+            collide_impl<L, N, S, T, true>(v, om, (T)(a.force_g * a.force_cos[y]), sig);
+            if (owner) {
+                ss += (double)sig[0] * a.force_sin[y];
+                sc += (double)sig[0] * a.force_cos[y];
+            }
+        } else {
+            collide<L, N, S, T>(v, om);
+        }
         if (owner) {
             const size_t o = r0 + (size_t)xo;
             const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
@@ -222,6 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
             });
         }
     }
+    if constexpr (F)
+        if (a.stress) store_stress<kBlock>(a.stress, ss, sc);
 }
 
 // ---------------------------------------------------------------- initial state
@@ -295,34 +358,37 @@ __global__ __launch_bounds__(kBlock) void k_encode(void *fv, uint32_t ps, uint32
     f[(size_t)a * ps + cell] = C::template enc<SR>((typename C::T)v, SR ? pop_bits(mix32(cell ^ key), a) : 0u);
 }
 
-// rho and u in FP64 from the stored state.
+// Index of a cell along the force axis.
+__device__ __forceinline__ uint32_t force_index(const DiagArgs &a, uint32_t cell) {
+    const uint32_t yz = cell / (uint32_t)a.nx;
+    return a.force_axis == 1 ? yz % (uint32_t)a.ny : yz / (uint32_t)a.ny;
+}
+
+// rho and the physical u in FP64 from the stored state (minus half the latest force).
 template <class L, int S>
-__global__ __launch_bounds__(kBlock) void k_moments(const void *fv, uint32_t ps, uint32_t ncell, double *rho,
-                                                    double *u) {
+__global__ __launch_bounds__(kBlock) void k_moments(DiagArgs a, double *rho, double *u) {
     using C = Codec<S>;
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= ncell) return;
-    const auto *f = static_cast<const typename C::raw *>(fv);
+    const auto *f = static_cast<const typename C::raw *>(a.f);
     double v[L::Q];
     static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        v[i] = C::dec64(f[(size_t)i * ps + cell]);
+        v[i] = C::dec64(f[(size_t)i * a.pstride + cell]);
     });
     const Moments<double> m = project<L, S>(v);
     const double r = C::dev ? 1.0 + m.d : m.d;
     rho[cell] = r;
-    u[cell] = m.jx / r;
+    double ux = m.jx / r;
+    if (a.half_g != 0.0) ux -= a.half_g * a.force_cos[force_index(a, cell)];
+    u[cell] = ux;
     u[ncell + cell] = m.jy / r;
     if (L::D == 3) u[2 * (size_t)ncell + cell] = m.jz / r;
 }
 
 // Deterministic FP64 reduction, stage 1: fixed grid-stride order per thread, fixed
-// butterfly per wave, fixed order over the waves of the block.
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
+// butterfly per wave (wave_sum), fixed order over the waves of the block.
 
 template <class L, int S>
 __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a) {
@@ -338,13 +404,18 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a) {
         });
         const Moments<double> m = project<L, S>(v);
         const double r = C::dev ? 1.0 + m.d : m.d;
-        const double ux = m.jx / r;
+        double ux = m.jx / r, jx = m.jx;
+        if (a.half_g != 0.0) {           // physical velocity and momentum: minus half the force
+            const double hg = a.half_g * a.force_cos[force_index(a, cell)];
+            ux -= hg;
+            jx -= r * hg;
+        }
         const uint32_t yz = cell / (uint32_t)a.nx;
         const uint32_t j = a.wave_axis == 1 ? yz % (uint32_t)a.ny : yz / (uint32_t)a.ny;
         acc[0] += ux * a.sin_tab[j];
         acc[1] += ux * a.cos_tab[j];
         acc[2] += m.d;
-        acc[3] += m.jx;
+        acc[3] += jx;
         acc[4] += m.jy;
         acc[5] += m.jz;
     }
@@ -377,19 +448,19 @@ __global__ __launch_bounds__(kBlock) void k_finite(const void *fv, uint32_t ps, 
 // ---------------------------------------------------------------- host launchers
 inline uint32_t blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
 
-template <class L, int N, int S, bool SR, int BLOCK, bool NTS>
+template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
 hipError_t launch_shift_rows(const StepArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_shift_rows<L, N, S, SR, BLOCK, NTS>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_shift_rows<L, N, S, SR, BLOCK, NTS, F>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
-template <class L, int N, int S, bool SR>
+template <class L, int N, int S, bool SR, bool F>
 hipError_t launch_shift_cells(const StepArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_shift_cells<L, N, S, SR>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_shift_cells<L, N, S, SR, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
-template <class L, int N, int S, bool SR, class T>
+template <class L, int N, int S, bool SR, class T, bool F>
 hipError_t launch_bw2(const StepArgs &a, const BWCoef<T> &cf, hipStream_t s) {
-    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
+    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
     return hipGetLastError();
 }
 template <class L, int N, int S>
@@ -418,8 +489,9 @@ hipError_t launch_encode(void *f, uint32_t ps, uint32_t ncell, int a, double add
     return hipGetLastError();
 }
 template <class L, int S>
-hipError_t launch_moments(const void *f, uint32_t ps, uint32_t ncell, double *rho, double *u, hipStream_t s) {
-    hipLaunchKernelGGL((k_moments<L, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, rho, u);
+hipError_t launch_moments(const DiagArgs &a, double *rho, double *u, hipStream_t s) {
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    hipLaunchKernelGGL((k_moments<L, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, a, rho, u);
     return hipGetLastError();
 }
 template <class L, int S>
@@ -444,15 +516,20 @@ KernelSet make_set() {
     k.storage = S;
     k.sr = SR ? 1 : 0;
     if constexpr (L::on_lattice) {
-        k.shift_rows[0] = &launch_shift_rows<L, N, S, SR, 256, false>;
-        k.shift_rows[1] = &launch_shift_rows<L, N, S, SR, 256, true>;
-        k.shift_rows[2] = &launch_shift_rows<L, N, S, SR, 512, true>;
-        k.shift_cells = &launch_shift_cells<L, N, S, SR>;
+        k.shift_rows[0] = &launch_shift_rows<L, N, S, SR, 256, false, false>;
+        k.shift_rows[1] = &launch_shift_rows<L, N, S, SR, 256, true, false>;
+        k.shift_rows[2] = &launch_shift_rows<L, N, S, SR, 512, true, false>;
+        k.shift_cells = &launch_shift_cells<L, N, S, SR, false>;
+        k.shift_rows_forced = &launch_shift_rows<L, N, S, SR, 256, false, true>;
+        k.shift_cells_forced = &launch_shift_cells<L, N, S, SR, true>;
     } else if constexpr (L::D == 2) {
-        if constexpr (S == ST_FP64)
-            k.bw2_f64 = &launch_bw2<L, N, S, SR, double>;
-        else
-            k.bw2_f32 = &launch_bw2<L, N, S, SR, float>;
+        if constexpr (S == ST_FP64) {
+            k.bw2_f64 = &launch_bw2<L, N, S, SR, double, false>;
+            k.bw2_f64_forced = &launch_bw2<L, N, S, SR, double, true>;
+        } else {
+            k.bw2_f32 = &launch_bw2<L, N, S, SR, float, false>;
+            k.bw2_f32_forced = &launch_bw2<L, N, S, SR, float, true>;
+        }
     }
     k.init_wave = &launch_init_wave<L, N, S>;
     k.init_fields = &launch_init_fields<L, N, S>;

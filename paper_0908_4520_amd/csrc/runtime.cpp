@@ -141,9 +141,24 @@ struct lbm_sim {
     uint32_t warnings = 0;
     BWCoef<float> bwf{};
     BWCoef<double> bwd{};
+    // body force F_x = f_amp cos(f_freq t) cos(2 pi j / N_w) along f_axis (Eq. force)
+    bool forced = false;
+    double f_amp = 0, f_freq = 0, f_dt = 0;
+    int f_axis = 0;
+    double *d_ftab = nullptr;       // cos then sin along the force axis
+    double *d_stress = nullptr;     // per-wave stress sums of the latest forced step
+    uint32_t stress_slots = 0;      // slots written by that step
+    uint32_t stress_cap = 0;        // slots allocated
+    bool stress_valid = false;
 };
 
 namespace {
+
+// Force times dt at the collision of step n (time n dt); zero before the first step.
+double force_g_at(const lbm_sim *s, int64_t n) {
+    if (!s->forced || n <= 0) return 0.0;
+    return s->f_amp * s->f_dt * cos(s->f_freq * (double)n * s->f_dt);
+}
 
 StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index) {
     StepArgs a{};
@@ -175,17 +190,38 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     return a;
 }
 
-hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index) {
-    const StepArgs a = step_args(s, fin, fout, tile_index);
+// One step from fin to fout with tile tile_index.  A forced simulation runs the forced
+// kernels; with record_stress they also store the per-wave stress sums.
+hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, bool record_stress) {
+    StepArgs a = step_args(s, fin, fout, tile_index);
+    const KernelSet *k = s->ks;
+    if (s->forced) {
+        a.force_g = force_g_at(s, s->nstep + 1);
+        a.force_cos = s->d_ftab;
+        a.force_sin = s->d_ftab + (s->f_axis == 1 ? s->g.ny : s->g.nz);
+        a.force_axis = s->f_axis;
+        if (record_stress) {
+            const uint32_t slots = a.nblocks * (uint32_t)(kBlock / 64);   // forced kernels: 256 threads
+            if (slots > s->stress_cap) return hipErrorInvalidValue;
+            a.stress = s->d_stress;
+            s->stress_slots = slots;
+        }
+        if (s->move == LBM_MOVE_BW2)
+            return s->o.storage == LBM_FP64 ? k->bw2_f64_forced(a, s->bwd, s->stream)
+                                            : k->bw2_f32_forced(a, s->bwf, s->stream);
+        return s->rows_ok ? k->shift_rows_forced(a, s->stream) : k->shift_cells_forced(a, s->stream);
+    }
     if (s->move == LBM_MOVE_BW2)
-        return s->o.storage == LBM_FP64 ? s->ks->bw2_f64(a, s->bwd, s->stream) : s->ks->bw2_f32(a, s->bwf, s->stream);
-    return s->rows_ok ? s->ks->shift_rows[kShiftTiles[tile_index].variant](a, s->stream)
-                      : s->ks->shift_cells(a, s->stream);
+        return s->o.storage == LBM_FP64 ? k->bw2_f64(a, s->bwd, s->stream) : k->bw2_f32(a, s->bwf, s->stream);
+    return s->rows_ok ? k->shift_rows[kShiftTiles[tile_index].variant](a, s->stream) : k->shift_cells(a, s->stream);
 }
+
+// The forced row kernel exists in the plain 256-thread form only: the first four shift tiles.
+constexpr int kForcedShiftTiles = 4;
 
 int tile_count(const lbm_sim *s) {
     if (s->move == LBM_MOVE_BW2) return (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
-    if (s->rows_ok) return (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]);
+    if (s->rows_ok) return s->forced ? kForcedShiftTiles : (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]);
     return 1;
 }
 
@@ -229,8 +265,11 @@ lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
     a.sin_tab = s->d_tab;
     a.cos_tab = s->d_tab + nw;
     a.partials = s->d_partials;
+    a.half_g = 0.5 * force_g_at(s, s->nstep);
+    a.force_cos = s->d_ftab;
+    a.force_axis = s->f_axis;
     HIP_TRY(s->ks->diag(a, s->diag_blocks, s->stream));
-    HIP_TRY(diag_final(s->d_partials, s->diag_blocks, s->d_result, s->stream));
+    HIP_TRY(diag_final(s->d_partials, s->diag_blocks, 6, s->d_result, s->stream));
     HIP_TRY(hipMemcpyAsync(out, s->d_result, 6 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return LBM_OK;
@@ -265,20 +304,20 @@ lbm_status lbm_lattice_info(lbm_lattice lat, int32_t *Q, int32_t *D, int32_t *c,
     return LBM_OK;
 }
 
-double lbm_tau_from_kn(lbm_lattice lat, lbm_move move, double kn, int32_t wavelength_cells, double cfl) {
+double lbm_time_step(lbm_lattice lat, lbm_move move, int32_t wavelength_cells, double cfl) {
     const LatInfo *L = lat_info((int)lat);
-    if (!L || !(kn >= 0.0) || wavelength_cells < 1) return NAN;
+    if (!L || wavelength_cells < 1) return NAN;
     if (move == LBM_MOVE_AUTO) move = L->on_lattice ? LBM_MOVE_SHIFT : LBM_MOVE_BW2;
     const double dx = 2.0 * M_PI / (double)wavelength_cells;
-    double dt;
-    if (move == LBM_MOVE_SHIFT) {
-        if (!L->on_lattice) return NAN;
-        dt = dx / L->scale;
-    } else {
-        if (!(cfl > 0.0 && cfl <= 1.0)) return NAN;
-        dt = cfl * dx / L->xi_max;
-    }
-    return kn / dt + 0.5;
+    if (move == LBM_MOVE_SHIFT) return L->on_lattice ? dx / L->scale : NAN;
+    if (move != LBM_MOVE_BW2 || !(cfl > 0.0 && cfl <= 1.0)) return NAN;
+    return cfl * dx / L->xi_max;
+}
+
+double lbm_tau_from_kn(lbm_lattice lat, lbm_move move, double kn, int32_t wavelength_cells, double cfl) {
+    if (!(kn >= 0.0)) return NAN;
+    const double dt = lbm_time_step(lat, move, wavelength_cells, cfl);
+    return isnan(dt) ? NAN : kn / dt + 0.5;
 }
 
 lbm_status lbm_init(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g) {
@@ -367,7 +406,7 @@ void lbm_free(lbm_sim *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     for (void *p : {s->buf[0], s->buf[1], (void *)s->d_tab, (void *)s->d_partials, (void *)s->d_result,
-                    (void *)s->d_flag})
+                    (void *)s->d_flag, (void *)s->d_ftab, (void *)s->d_stress})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -407,6 +446,7 @@ lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double r
     HIP_TRY(s->ks->init_wave(a, s->stream));
     s->cur = 0;
     s->nstep = 0;
+    s->stress_valid = false;
     return LBM_OK;
 }
 
@@ -423,6 +463,7 @@ lbm_status lbm_init_equilibrium(lbm_sim *s, const double *rho, const double *u) 
     HIP_TRY(e);
     s->cur = 0;
     s->nstep = 0;
+    s->stress_valid = false;
     return LBM_OK;
 }
 
@@ -430,9 +471,10 @@ lbm_status lbm_step(lbm_sim *s, int64_t n) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
     for (int64_t k = 0; k < n; ++k) {
-        HIP_TRY(launch_step(s, s->buf[s->cur], s->buf[s->cur ^ 1], s->tile));
+        HIP_TRY(launch_step(s, s->buf[s->cur], s->buf[s->cur ^ 1], s->tile, true));
         s->cur ^= 1;
         s->nstep += 1;
+        s->stress_valid = s->forced;
         if (s->o.check_every > 0 && s->nstep % s->o.check_every == 0) {
             HIP_TRY(fill_zero(s->d_flag, 1, s->stream));
             HIP_TRY(s->ks->finite(s->buf[s->cur], s->pstride, (uint32_t)s->ncell, s->L->Q, s->d_flag, s->stream));
@@ -450,7 +492,16 @@ lbm_status lbm_moments(lbm_sim *s, double *rho, double *u) {
     const size_t n = s->ncell, D = (size_t)s->L->D;
     double *d = nullptr;
     HIP_TRY(hipMalloc(&d, sizeof(double) * n * (1 + D)));
-    hipError_t e = s->ks->moments(s->buf[s->cur], s->pstride, (uint32_t)n, d, d + n, s->stream);
+    DiagArgs a{};
+    a.f = s->buf[s->cur];
+    a.nx = s->g.nx;
+    a.ny = s->g.ny;
+    a.nz = s->g.nz;
+    a.pstride = s->pstride;
+    a.half_g = 0.5 * force_g_at(s, s->nstep);
+    a.force_cos = s->d_ftab;
+    a.force_axis = s->f_axis;
+    hipError_t e = s->ks->moments(a, d, d + n, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rho, d, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(u, d + n, sizeof(double) * n * D, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -516,6 +567,7 @@ lbm_status lbm_set_populations(lbm_sim *s, const double *f) {
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     }
     (void)hipFree(d);
+    s->stress_valid = false;
     HIP_TRY(e);
     return LBM_OK;
 }
@@ -548,6 +600,7 @@ lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes) {
     lbm_status st = lbm_state_bytes(s, &need);
     if (st != LBM_OK) return st;
     if (!host || bytes != need) return fail(LBM_EINVAL, "state needs exactly %lld bytes", (long long)need);
+    s->stress_valid = false;
     HIP_TRY(hipMemcpyAsync(s->buf[s->cur], host, (size_t)need, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return LBM_OK;
@@ -576,6 +629,105 @@ lbm_status lbm_fit_decay(const double *amp, const int64_t *steps, int64_t count,
         }
     if (!(sxx > 0.0)) return fail(LBM_EINVAL, "fit window has a single distinct step");
     *gamma = sxy / sxx;
+    return LBM_OK;
+}
+
+lbm_status lbm_fit_oscillation(const double *amp, const int64_t *steps, int64_t count, double dt, double frequency,
+                               int64_t n_first, int64_t n_last, double *re, double *im) {
+    if (!amp || !steps || !re || !im || count < 0) return fail(LBM_EINVAL, "NULL argument or negative count");
+    if (!(dt > 0.0) || !isfinite(frequency)) return fail(LBM_EINVAL, "dt must be > 0 and frequency finite");
+    // least squares for amp(n) = a cos(w t) + b sin(w t), t = n dt; z = a - i b
+    double scc = 0, sss = 0, scs = 0, sac = 0, sas = 0, sa = 0;
+    int64_t m = 0;
+    for (int64_t k = 0; k < count; ++k)
+        if (steps[k] >= n_first && steps[k] <= n_last) {
+            if (!isfinite(amp[k])) return fail(LBM_EINVAL, "amplitude %lld is not finite", (long long)k);
+            const double ph = frequency * (double)steps[k] * dt, c = cos(ph), sn = sin(ph);
+            scc += c * c;
+            sss += sn * sn;
+            scs += c * sn;
+            sac += amp[k] * c;
+            sas += amp[k] * sn;
+            sa += amp[k];
+            ++m;
+        }
+    if (m < 1) return fail(LBM_EINVAL, "no point in the fit window");
+    if (frequency == 0.0) {
+        *re = sa / (double)m;
+        *im = 0.0;
+        return LBM_OK;
+    }
+    const double det = scc * sss - scs * scs;
+    if (!(fabs(det) > 1e-12 * scc * sss)) return fail(LBM_EINVAL, "fit window does not resolve the oscillation");
+    const double a = (sac * sss - sas * scs) / det, b = (sas * scc - sac * scs) / det;
+    *re = a;
+    *im = -b;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_force(lbm_sim *s, double amplitude, double frequency, int32_t wave_axis) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (wave_axis == 0) {                       // back to the unforced kernels
+        s->forced = false;
+        s->stress_valid = false;
+        return LBM_OK;
+    }
+    lbm_status st = check_axis(s, wave_axis);
+    if (st != LBM_OK) return st;
+    if (s->move == LBM_MOVE_BW2 && wave_axis != 1) return fail(LBM_EINVAL, "upwind advection is two-dimensional");
+    if (!isfinite(amplitude) || !isfinite(frequency)) return fail(LBM_EINVAL, "amplitude and frequency must be finite");
+    const int nw = wave_axis == 1 ? s->g.ny : s->g.nz;
+    const double dt = lbm_time_step((lbm_lattice)s->L->id, s->move, nw, s->o.cfl);
+    if (!(dt > 0.0)) return fail(LBM_EINVAL, "no time step for this configuration");
+    std::vector<double> h(2 * (size_t)nw);
+    for (int j = 0; j < nw; ++j) {
+        const double ph = 2.0 * M_PI * (double)j / (double)nw;
+        h[j] = cos(ph);
+        h[nw + j] = sin(ph);
+    }
+    // stress slots: the largest grid of the forced kernels (256 threads) over the tiles
+    const bool was = s->forced;
+    s->forced = true;
+    uint32_t cap = 0;
+    for (int t = 0; t < tile_count(s); ++t)
+        cap = std::max(cap, step_args(s, s->buf[0], s->buf[1], t).nblocks * (uint32_t)(kBlock / 64));
+    s->forced = was;
+    double *tab = nullptr, *stress = nullptr;
+    hipError_t e = hipMalloc(&tab, sizeof(double) * h.size());
+    if (e == hipSuccess) e = hipMalloc(&stress, sizeof(double) * 2 * (size_t)cap);
+    if (e == hipSuccess) e = hipMemcpyAsync(tab, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        if (tab) (void)hipFree(tab);
+        if (stress) (void)hipFree(stress);
+        HIP_TRY(e);
+    }
+    if (s->d_ftab) (void)hipFree(s->d_ftab);
+    if (s->d_stress) (void)hipFree(s->d_stress);
+    s->d_ftab = tab;
+    s->d_stress = stress;
+    s->stress_cap = cap;
+    s->forced = true;
+    s->f_amp = amplitude;
+    s->f_freq = frequency;
+    s->f_dt = dt;
+    s->f_axis = wave_axis;
+    s->stress_valid = false;
+    s->tile = std::min(s->tile, tile_count(s) - 1);
+    return LBM_OK;
+}
+
+lbm_status lbm_shear_stress_amplitude(lbm_sim *s, double *s_sin, double *s_cos) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (!s->forced || !s->stress_valid)
+        return fail(LBM_ESTATE, "no forced step since the force or the state was set");
+    HIP_TRY(diag_final(s->d_stress, s->stress_slots, 2, s->d_result, s->stream));
+    double r[2];
+    HIP_TRY(hipMemcpyAsync(r, s->d_result, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double scale = 2.0 / (double)s->ncell;
+    if (s_sin) *s_sin = scale * r[0];
+    if (s_cos) *s_cos = scale * r[1];
     return LBM_OK;
 }
 
@@ -617,11 +769,11 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile,
     const int64_t saved_step = s->nstep;
     for (int t = 0; t < tile_count(s) && e == hipSuccess; ++t) {
         int c = 0;
-        e = launch_step(s, scratch[c], scratch[c ^ 1], t);   // warm-up
+        e = launch_step(s, scratch[c], scratch[c ^ 1], t, false);   // warm-up
         c ^= 1;
         if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
         for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k) {
-            e = launch_step(s, scratch[c], scratch[c ^ 1], t);
+            e = launch_step(s, scratch[c], scratch[c ^ 1], t, false);
             c ^= 1;
         }
         if (e == hipSuccess) e = hipEventRecord(e1, s->stream);

@@ -54,6 +54,11 @@ SIGNATURES = {
     "lbm_opts_default": (None, [ctypes.POINTER(lbm_opts)]),
     "lbm_lattice_info": (ctypes.c_int, [ctypes.c_int, _I32, _I32, _I32, _D, _D]),
     "lbm_tau_from_kn": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int32, ctypes.c_double]),
+    "lbm_time_step": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_double]),
+    "lbm_set_force": (ctypes.c_int, [_SIM, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "lbm_shear_stress_amplitude": (ctypes.c_int, [_SIM, _D, _D]),
+    "lbm_fit_oscillation": (ctypes.c_int, [_D, _I64, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                           ctypes.c_int64, _D, _D]),
     "lbm_init": (ctypes.c_int, [ctypes.POINTER(_SIM), ctypes.c_int, ctypes.c_int32, ctypes.c_double, lbm_grid]),
     "lbm_init_ex": (ctypes.c_int, [ctypes.POINTER(_SIM), ctypes.c_int, ctypes.c_int32, ctypes.c_double, lbm_grid,
                                    ctypes.POINTER(lbm_opts)]),
@@ -146,6 +151,23 @@ def lbm_tau_from_kn(lattice: str, kn: float, wavelength_cells: int, move: str = 
     return t
 
 
+def lbm_time_step(lattice: str, wavelength_cells: int, move: str = "auto", cfl: float = 0.5) -> float:
+    t = _lib.lbm_time_step(LATTICES[lattice], MOVES[move], wavelength_cells, cfl)
+    if math.isnan(t):
+        raise ValueError("invalid arguments to lbm_time_step")
+    return t
+
+
+def lbm_fit_oscillation(amp, steps, dt: float, frequency: float, n_first: int, n_last: int) -> complex:
+    """Complex amplitude z of amp ~ Re(z e^{i frequency steps dt}) (least squares in the window)."""
+    a = np.ascontiguousarray(amp, dtype=np.float64)
+    st = np.ascontiguousarray(steps, dtype=np.int64)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.lbm_fit_oscillation(_dp(a), st.ctypes.data_as(_I64), len(a), dt, frequency, n_first, n_last,
+                                    ctypes.byref(re), ctypes.byref(im)))
+    return complex(re.value, im.value)
+
+
 def lbm_fit_decay(amp, steps, n_first: int, n_last: int) -> float:
     amp = np.ascontiguousarray(amp, dtype=np.float64)
     st = np.ascontiguousarray(steps, dtype=np.int64)
@@ -225,6 +247,16 @@ class Sim:
         s, c = ctypes.c_double(), ctypes.c_double()
         _check(_lib.lbm_shear_amplitude(self._h, wave_axis, ctypes.byref(s), ctypes.byref(c)))
         return s.value, c.value
+
+    def set_force(self, amplitude: float, frequency: float, wave_axis: int):
+        """Oscillating body force F_x = amplitude cos(frequency t) cos(2 pi j/N_w); axis 0 = off."""
+        _check(_lib.lbm_set_force(self._h, amplitude, frequency, wave_axis))
+
+    def shear_stress_amplitude(self):
+        """(S_sin, S_cos) of the physical shear stress at the latest forced collision."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.lbm_shear_stress_amplitude(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def totals(self):
         m = ctypes.c_double()
