@@ -132,3 +132,38 @@ def forced_response(vs, omega, n_w, wave_axis, mode, G0, phi_dt, cfl=0.5):
     s_c = sp + np.conj(sm)
     s_s = 1j * sp - 1j * np.conj(sm)
     return complex(u_s), complex(u_c), complex(s_s), complex(s_c)
+
+
+# ------------------------------------------------------------------ reduced DVM (Eqs. ga, gb)
+# The reduced model is linear in G: with G(j) = Re(Ghat e^{i k j}), one step maps
+#     Ghat <- C S Ghat + b cos(phi t_{n+1}),  S = diag(Beam-Warming factors of xi_k dt/dy),
+#     C = I - omega (I - 1 w^T),  b = A dt 1,
+# (the +dt F/2 in u, relaxed with weight omega, and the source with weight 1 - omega/2 add to
+# dt F); the velocity projection is Re(w . Ghat) - A dt cos(phi t_n)/2 and the stress of the
+# collision at t_n is (1 - omega/2) sum_k w_k xi_k (S Ghat(n-1))_k (sine projection -Im).
+
+def _reduced_parts(nodes, kn, n_w, cfl):
+    from .lattices import gauss_hermite_1d
+    xi, w = gauss_hermite_1d(nodes)
+    dt = cfl * (2.0 * math.pi / n_w) / float(np.max(np.abs(xi)))
+    omega = 0.0 if math.isinf(kn) else dt / (kn + 0.5 * dt)
+    theta = 2.0 * math.pi / n_w
+    S = np.array([bw_factor(x * dt / theta, theta) for x in xi])
+    C = np.eye(nodes) - omega * (np.eye(nodes) - np.outer(np.ones(nodes), w))
+    return xi, w, dt, omega, C @ np.diag(S), S
+
+
+def reduced_response(nodes, kn, n_w, amplitude, frequency, cfl=0.5):
+    """Complex amplitudes (velocity cosine projection, stress sine projection) of the periodic
+    state: P(n) = Re(z e^{i frequency n dt})."""
+    xi, w, dt, omega, M, S = _reduced_parts(nodes, kn, n_w, cfl)
+    b = amplitude * dt * np.ones(nodes, dtype=np.complex128)
+    e = np.exp(1j * frequency * dt)
+    I = np.eye(nodes)
+    Xp = np.linalg.solve(e * I - M, 0.5 * b * e)
+    Xm = np.linalg.solve(np.conj(e) * I - M, 0.5 * b * np.conj(e))
+    u = w @ Xp + np.conj(w @ Xm) - 0.5 * amplitude * dt
+    v = (1.0 - 0.5 * omega) * w * xi * S
+    sp, sm = (v @ Xp) / e, (v @ Xm) * e
+    s = 1j * sp - 1j * np.conj(sm)
+    return complex(u), complex(s)
