@@ -10,7 +10,9 @@ cell.  Prints one JSON line.
 
 Besides the main workload the JSON line carries "variants": the 512^3 D3Q39 step with FP32,
 BF16 and FP16 deviation storage (stochastic rounding), the D2Q16-GH DVM step at 2048^2, the
-full-f FP32 ablation, the 4 x 64 D2Q9 FP64 case, and the 256-instance batched Kn sweep.
+full-f FP32 ablation, the 4 x 64 D2Q9 FP64 case, the forced step (oscillating body force,
+amplitude 1e-3, frequency 0.25) for D2Q37 and D2Q25-CK, the Table-1 sets D2Q16-CK, D2Q17,
+D2Q21, D2Q25-CK at 4096^2, and the 256-instance batched Kn sweep.
 """
 from __future__ import annotations
 
@@ -62,12 +64,16 @@ def time_steps(sim, steps, stream, torch):
     return start.elapsed_time(end) / steps
 
 
-def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, warmup, sr=False, noise=0.0):
+def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, warmup, sr=False, noise=0.0,
+                force=None):
+    """force = (amplitude, frequency): the oscillating body force along the same wave axis."""
     from paper_0908_4520_amd import counters
     n_w = grid[axis]
     tau = lbm.lbm_tau_from_kn(lattice, kn, n_w)
     with lbm.Sim(lattice, N, tau, grid, storage=storage, stream=stream.cuda_stream, stochastic_round=sr,
                  sr_seed=12345) as s:
+        if force is not None:
+            s.set_force(force[0], force[1], axis)
         s.set_shear_wave(1e-3, axis, rho_noise=noise, seed=1)
         tile, _ = s.autotune(3)
         info = s.tile_info(tile)
@@ -104,6 +110,46 @@ def run_batch(lbm, torch, stream, steps=5000, record_every=50):
                     gbs=b.bytes_per_step * steps / (ms * 1e-3) / 1e9, cells=b.cells, steps=steps,
                     form=form, block=block, bytes_per_step=b.bytes_per_step,
                     note="effective GB/s: the 115 MB state is resident in the 256 MB Infinity Cache")
+
+
+def run_rdvm(lbm, torch, stream, steps=4000):
+    """The reduced discrete-velocity sweep of the forced wave: 256 instances (20 Gauss-Hermite
+    velocities x 128 cells each), all advanced in one persistent launch per run."""
+    from paper_0908_4520_amd import workloads
+    inst = workloads.rdvm_instances(0, 256)
+    with lbm.ReducedDVM(inst, stream=stream.cuda_stream) as d:
+        d.run(200, 0)                                   # warm-up
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        d.run(steps, 0)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+    updates = sum(m * nw for m, nw, *_ in inst) * steps
+    # LDS traffic per update: three 8-byte reads (the upwind stencil) and one 8-byte write
+    lds_peak = 128 * 2.4e9 * 256
+    return dict(ms_per_step=ms / steps, updates_per_s=updates / (ms * 1e-3), steps=steps,
+                instances=len(inst), lds_gbs=32 * updates / (ms * 1e-3) / 1e9,
+                lds_frac=32 * updates / (ms * 1e-3) / lds_peak,
+                note="state resident in LDS for the whole run; bound: LDS bandwidth (128 B/clk/CU)")
+
+
+def rdvm_cpu_baseline(target_seconds=5.0):
+    """The oracle's reduced model (numpy) on one instance of the sweep: updates per second."""
+    from oracle import reduced_dvm
+    from paper_0908_4520_amd import workloads
+    m, nw, kn, amp, phi = workloads.rdvm_instances(0, 256)[1]
+    r = reduced_dvm.ReducedDVM(m, nw, kn, amp, phi)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < target_seconds:
+        r.step(50)
+        n += 50
+    dt = time.perf_counter() - t0
+    return {"value": m * nw * n / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one instance ({m} velocities x {nw} cells), {n} steps in {dt:.1f} s"}
 
 
 def copy_bandwidth(torch, nbytes, reps=20):
@@ -186,6 +232,12 @@ def main():
             ("D2Q16-GH_2048^2_N3_bw2_fp32_dev", dict(lattice="D2Q16-GH", N=3, kn=1.0, grid=(2048, 2048, 1), storage="fp32_dev", axis=1)),
             ("D2Q37_4096^2_N4_fp32_full", dict(lattice="D2Q37", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32", axis=1, noise=1e-6)),
             ("D2Q9_4x64_N2_fp64", dict(lattice="D2Q9", N=2, kn=0.1, grid=(4, 64, 1), storage="fp64", axis=1)),
+            ("D2Q37_4096^2_N4_fp32_dev_forced", dict(lattice="D2Q37", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1, force=(1e-3, 0.25))),
+            ("D2Q16-CK_4096^2_N3_fp32_dev", dict(lattice="D2Q16-CK", N=3, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1)),
+            ("D2Q17_4096^2_N3_fp32_dev", dict(lattice="D2Q17", N=3, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1)),
+            ("D2Q21_4096^2_N3_fp32_dev", dict(lattice="D2Q21", N=3, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1)),
+            ("D2Q25-CK_4096^2_N4_fp32_dev", dict(lattice="D2Q25-CK", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1)),
+            ("D2Q25-CK_4096^2_N4_fp32_dev_forced", dict(lattice="D2Q25-CK", N=4, kn=0.1, grid=(4096, 4096, 1), storage="fp32_dev", axis=1, force=(1e-3, 0.25))),
         ]:
             log(f"timing {name} ...")
             steps = 2000 if name.startswith("D2Q9") else min(args.steps, 200)
@@ -197,6 +249,13 @@ def main():
         variants["batch_256_instances_5000_steps_fp32_dev"] = {k: (round(v, 4) if isinstance(v, float) else v)
                                                                for k, v in r.items()}
         log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS (form {r['form']}, block {r['block']})")
+        log("timing the 256-instance reduced-DVM sweep (4000 steps) ...")
+        r = run_rdvm(lbm, torch, stream)
+        if not args.no_cpu_baseline:
+            r["cpu_oracle"] = rdvm_cpu_baseline()
+        variants["rdvm_256_instances_M20_Nw128_fp64"] = {k: (round(v, 6) if isinstance(v, float) else v)
+                                                         for k, v in r.items()}
+        log(f"  {r['ms_per_step']:.4f} ms/step, {r['updates_per_s']:.3e} updates/s, LDS {r['lds_frac']:.1%} of peak")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -269,6 +269,51 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
 void lbm_batch_free(lbm_batch *b);   /* NULL-safe */
 
+/* ---- Reduced discrete-velocity model of the forced standing shear wave (section 4, Eqs. ga
+ * and gb): the linearised BGK equation of Eq. LBGK with xi_x integrated out.  Started from
+ * rest, G_a stays zero (Eq. ga has no source), so an instance carries G_b on the M-point
+ * Gauss-Hermite rule in xi_y (lbm_gauss_hermite; u_x = sum_k w_k G_b(xi_k)) times N_w periodic
+ * cells of y in [0, 2 pi) (one wavelength), driven by F_x = amplitude cos(frequency t)
+ * cos(2 pi j / N_w).  One step: Beam-Warming advection of every velocity at Courant number
+ * xi_k dt / dy, dt = cfl dy / max|xi_k|, then the second-order relaxation and source of
+ * Eq. 2order on the shifted variable G~ = G + dt/(2 Kn)(G - u_x) - dt F_x / 2:
+ *   u_x = sum_k w_k G~_k + dt F_x / 2,   G~_k <- G~_k - omega (G~_k - u_x) + (1 - omega/2) dt F_x,
+ * omega = dt / (Kn + dt/2), F_x at the step's collision time t = n dt.  FP64 throughout. */
+typedef struct {
+    int32_t nodes;       /* Gauss-Hermite points M in xi_y, 2..64 */
+    int32_t cells;       /* N_w, 1..256 */
+    double kn;           /* Knudsen number > 0 (INFINITY = collisionless) */
+    double amplitude;    /* force amplitude A (units of Eq. nondime) */
+    double frequency;    /* force frequency phi (0 = steady force) */
+} lbm_rdvm_instance;
+typedef struct lbm_rdvm lbm_rdvm;
+
+/* The n-point Gauss-Hermite rule (2 <= n <= 64) for the weight exp(-x^2/2)/sqrt(2 pi): nodes
+ * ascending and weights summing to 1 (tables generated in 60-digit arithmetic).  Host only;
+ * either pointer may be NULL.  LBM_EINVAL for n out of range. */
+lbm_status lbm_gauss_hermite(int32_t n, double *nodes, double *weights);
+
+/* count >= 1 instances at rest (G~ = 0, step 0), advanced together: one workgroup per instance
+ * keeps its whole state in on-chip memory for a run.  cfl in (0, 1].  hip_stream may be NULL
+ * (the default stream).  Copies inst. */
+lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_t count, double cfl,
+                           void *hip_stream);
+/* All instances back to rest, step 0. */
+lbm_status lbm_rdvm_reset(lbm_rdvm *r);
+/* Advance all instances by steps >= 0 steps in one launch.  With record_every >= 1 and
+ * non-NULL arrays, after every record_every steps of this run it records per instance the
+ * cosine projection of the velocity, (2/N_w) sum_j u_x(j) cos(2 pi j/N_w), into
+ * velocity[i * nrec + k], and the sine projection of the shear stress sum_k w_k xi_k G_k
+ * (G the distribution behind G~, G - u_x = (1 - omega/2)(G~ - u_x + dt F/2)) into
+ * stress[i * nrec + k], nrec = steps / record_every, both at the collision of that step.
+ * Synchronises before returning. */
+lbm_status lbm_rdvm_run(lbm_rdvm *r, int64_t steps, int32_t record_every, double *velocity, double *stress);
+/* FP64 copy of instance `index`'s state G~[k * N_w + j] (M * N_w values). */
+lbm_status lbm_rdvm_state(lbm_rdvm *r, int32_t index, double *g);
+/* Time step, omega and the step count (shared by all instances); any pointer may be NULL. */
+lbm_status lbm_rdvm_info(const lbm_rdvm *r, int32_t index, double *dt, double *omega, int64_t *step);
+void lbm_rdvm_free(lbm_rdvm *r);   /* NULL-safe */
+
 /* Thread-local text of the last error (empty string if none). */
 const char *lbm_last_error(void);
 

@@ -167,3 +167,19 @@ def reduced_response(nodes, kn, n_w, amplitude, frequency, cfl=0.5):
     sp, sm = (v @ Xp) / e, (v @ Xm) * e
     s = 1j * sp - 1j * np.conj(sm)
     return complex(u), complex(s)
+
+
+def reduced_series(nodes, kn, n_w, amplitude, frequency, steps, every, cfl=0.5):
+    """Velocity cosine and stress sine projections after every `every` steps from rest."""
+    xi, w, dt, omega, M, S = _reduced_parts(nodes, kn, n_w, cfl)
+    G = np.zeros(nodes, dtype=np.complex128)
+    b = amplitude * dt * np.ones(nodes)
+    v = (1.0 - 0.5 * omega) * w * xi * S
+    u_out, s_out = [], []
+    for n in range(1, steps + 1):
+        s = v @ G
+        G = M @ G + b * math.cos(frequency * n * dt)
+        if n % every == 0:
+            u_out.append((w @ G).real - 0.5 * amplitude * dt * math.cos(frequency * n * dt))
+            s_out.append(-s.imag)
+    return np.array(u_out), np.array(s_out)

@@ -16,6 +16,12 @@ omega(xi) = (2 pi)^{-D/2} exp(-xi^2/2), summing to 1):
     weights from the symmetric tridiagonal (Golub-Welsch) eigenproblem of the probabilists'
     Hermite recurrence He_{k+1} = x He_k - k He_{k-1}.
 Each double is the correctly rounded value of the 60-digit result, written as a hex float.
+
+gh_rules.inc: the n-point Gauss-Hermite rules for n = 2..64 (the velocity grids of the reduced
+discrete-velocity model), weight e^{-x^2/2}/sqrt(2 pi).  The nodes are the roots of He_n, found
+one per interval between consecutive roots of He_{n-1} (the roots of successive orthogonal
+polynomials interlace) by bisection and Newton steps in 60-digit arithmetic; the weights are
+n! / (n^2 He_{n-1}(x)^2).
 """
 from __future__ import annotations
 
@@ -29,6 +35,8 @@ mp.mp.dps = 60
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "lattices.inc")
+OUT_GH = os.path.join(HERE, "gh_rules.inc")
+GH_MAX = 64
 
 
 def orbit(v):
@@ -139,6 +147,74 @@ def golub_welsch(n):
     return [nodes[i] for i in order], [weights[i] for i in order]
 
 
+def hermite_e(n, x):
+    """He_n(x) and He_{n-1}(x) by the three-term recurrence."""
+    p0, p1 = mp.mpf(1), x
+    if n == 0:
+        return p0, mp.mpf(0)
+    for k in range(1, n):
+        p0, p1 = p1, x * p1 - k * p0
+    return p1, p0
+
+
+def gh_roots(n, prev):
+    """Roots of He_n, ascending; prev are the roots of He_{n-1} (they separate them)."""
+    bound = mp.sqrt(4 * n + 2) + 1
+    edges = [-bound] + list(prev) + [bound]
+    roots = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        flo = hermite_e(n, lo)[0]
+        for _ in range(30):                         # bisection into Newton's basin
+            mid = (lo + hi) / 2
+            fm = hermite_e(n, mid)[0]
+            if (fm < 0) == (flo < 0):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        x = (lo + hi) / 2
+        for _ in range(100):                        # Newton: He_n' = n He_{n-1}
+            f, fm1 = hermite_e(n, x)
+            dx = f / (n * fm1)
+            x -= dx
+            if abs(dx) < mp.mpf(10) ** (-55) * max(1, abs(x)):
+                break
+        else:
+            raise RuntimeError(f"Newton did not converge for He_{n}")
+        roots.append(x)
+    return roots
+
+
+def gh_rules(nmax):
+    rules, prev = {}, [mp.mpf(0)]                   # He_1 has the root 0
+    for n in range(2, nmax + 1):
+        xs = gh_roots(n, prev)
+        fact = mp.factorial(n)
+        ws = [fact / (n * n * hermite_e(n - 1, x)[0] ** 2) for x in xs]
+        rules[n] = (xs, ws)
+        prev = xs
+    return rules
+
+
+def emit_gh(rules):
+    lines = ["// gh_rules.inc -- generated by gen_lattices.py: n-point Gauss-Hermite rules for the",
+             "// weight exp(-x^2/2)/sqrt(2 pi), n = 2..64, nodes ascending.  Do not edit by hand.",
+             "#pragma once", "", "namespace lbm {", "",
+             f"constexpr int kGHMin = 2, kGHMax = {max(rules)};"]
+    offs, nodes, weights, o = [], [], [], 0
+    for n in range(2, max(rules) + 1):
+        offs.append(o)
+        nodes += rules[n][0]
+        weights += rules[n][1]
+        o += n
+    lines.append("// rule n occupies [kGHOffset[n - kGHMin], + n) of kGHNodes / kGHWeights")
+    lines.append("constexpr int kGHOffset[] = {" + ", ".join(str(v) for v in offs) + "};")
+    lines.append("constexpr double kGHNodes[] = {" + ", ".join(hexd(v) for v in nodes) + "};")
+    lines.append("constexpr double kGHWeights[] = {" + ", ".join(hexd(v) for v in weights) + "};")
+    lines.append("")
+    lines.append("}  // namespace lbm")
+    return "\n".join(lines) + "\n"
+
+
 def shell_set(shells, D, wts, r):
     c, xi, w = [], [], []
     for s, wt in zip(shells, wts):
@@ -243,10 +319,13 @@ def emit(sets):
 
 def main(argv):
     text = emit(build_all())
+    gh = emit_gh(gh_rules(GH_MAX))
     if len(argv) > 1 and argv[1] == "--check":
-        return 0 if open(OUT).read() == text else 1
+        return 0 if open(OUT).read() == text and open(OUT_GH).read() == gh else 1
     with open(OUT, "w") as fh:
         fh.write(text)
+    with open(OUT_GH, "w") as fh:
+        fh.write(gh)
     return 0
 
 

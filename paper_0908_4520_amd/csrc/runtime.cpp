@@ -1271,3 +1271,184 @@ lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block) {
 }
 
 }  // extern "C"
+
+// ======================================================================== reduced DVM
+#include "gh_rules.inc"
+#include "rdvm.h"
+
+struct lbm_rdvm {
+    int count = 0;
+    double cfl = 0.5;
+    hipStream_t stream = nullptr;
+    std::vector<lbm_rdvm_instance> inst;
+    std::vector<RdvmInst> desc;
+    RdvmInst *d_inst = nullptr;
+    double *d_nodes = nullptr, *d_tabs = nullptr, *d_state = nullptr, *d_log = nullptr;
+    size_t state_elems = 0, log_cap = 0, lds_bytes = 0;
+    int64_t nstep = 0;
+};
+
+extern "C" {
+
+lbm_status lbm_gauss_hermite(int32_t n, double *nodes, double *weights) {
+    if (n < kGHMin || n > kGHMax) return fail(LBM_EINVAL, "Gauss-Hermite rules exist for %d..%d points", kGHMin, kGHMax);
+    const int o = kGHOffset[n - kGHMin];
+    for (int k = 0; k < n; ++k) {
+        if (nodes) nodes[k] = kGHNodes[o + k];
+        if (weights) weights[k] = kGHWeights[o + k];
+    }
+    return LBM_OK;
+}
+
+void lbm_rdvm_free(lbm_rdvm *r) {
+    if (!r) return;
+    (void)hipStreamSynchronize(r->stream);
+    for (void *p : {(void *)r->d_inst, (void *)r->d_nodes, (void *)r->d_tabs, (void *)r->d_state, (void *)r->d_log})
+        if (p) (void)hipFree(p);
+    delete r;
+}
+
+lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_t count, double cfl, void *hip_stream) {
+    if (!out || !inst) return fail(LBM_EINVAL, "NULL argument");
+    if (count < 1) return fail(LBM_EINVAL, "count must be >= 1");
+    if (!(cfl > 0.0 && cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1], got %g", cfl);
+    std::vector<double> nodes, tabs;
+    std::vector<RdvmInst> desc((size_t)count);
+    size_t state = 0, maxv = 0;
+    for (int i = 0; i < count; ++i) {
+        const lbm_rdvm_instance &q = inst[i];
+        if (q.nodes < kGHMin || q.nodes > kRdvmMaxNodes)
+            return fail(LBM_EINVAL, "instance %d: nodes must be in [%d, %d]", i, kGHMin, kRdvmMaxNodes);
+        if (q.cells < 1 || q.cells > kRdvmBlock)
+            return fail(LBM_EINVAL, "instance %d: cells must be in [1, %d]", i, kRdvmBlock);
+        if ((size_t)q.nodes * (size_t)q.cells > (size_t)kRdvmMaxValues)
+            return fail(LBM_EINVAL, "instance %d: nodes * cells exceeds %d", i, kRdvmMaxValues);
+        if (!(q.kn > 0.0) || !isfinite(q.amplitude) || !isfinite(q.frequency))
+            return fail(LBM_EINVAL, "instance %d: kn must be > 0 (or +inf), amplitude and frequency finite", i);
+        const int M = q.nodes, nw = q.cells, o = kGHOffset[M - kGHMin];
+        const double ximax = fabs(kGHNodes[o + M - 1]);
+        RdvmInst &d = desc[(size_t)i];
+        d.M = M;
+        d.nw = nw;
+        d.dt = cfl * (2.0 * M_PI / (double)nw) / ximax;
+        d.omega = isinf(q.kn) ? 0.0 : d.dt / (q.kn + 0.5 * d.dt);
+        d.amp = q.amplitude;
+        d.freq = q.frequency;
+        d.node_off = (uint32_t)nodes.size();
+        for (int k = 0; k < M; ++k) nodes.push_back(kGHNodes[o + k]);
+        for (int k = 0; k < M; ++k) nodes.push_back(kGHWeights[o + k]);
+        for (int k = 0; k < M; ++k) {
+            const double A = fabs(kGHNodes[o + k]) * cfl / ximax;   // |Courant number|
+            nodes.push_back(A + 0.5 * A * (1.0 - A));
+        }
+        for (int k = 0; k < M; ++k) {
+            const double A = fabs(kGHNodes[o + k]) * cfl / ximax;
+            nodes.push_back(0.5 * A * (1.0 - A));
+        }
+        d.tab_off = (uint32_t)tabs.size();
+        for (int j = 0; j < nw; ++j) tabs.push_back(cos(2.0 * M_PI * (double)j / (double)nw));
+        for (int j = 0; j < nw; ++j) tabs.push_back(sin(2.0 * M_PI * (double)j / (double)nw));
+        d.state_off = state;
+        state += (size_t)M * nw;
+        maxv = std::max(maxv, (size_t)M * nw);
+    }
+    lbm_rdvm *r = new lbm_rdvm();
+    r->count = count;
+    r->cfl = cfl;
+    r->stream = (hipStream_t)hip_stream;
+    r->inst.assign(inst, inst + count);
+    r->desc = desc;
+    r->state_elems = state;
+    r->lds_bytes = sizeof(double) * (maxv + kRdvmBlock / 64);
+    hipError_t e = rdvm_allow_lds(r->lds_bytes);
+    if (e == hipSuccess) e = hipMalloc(&r->d_inst, sizeof(RdvmInst) * desc.size());
+    if (e == hipSuccess) e = hipMalloc(&r->d_nodes, sizeof(double) * nodes.size());
+    if (e == hipSuccess) e = hipMalloc(&r->d_tabs, sizeof(double) * tabs.size());
+    if (e == hipSuccess) e = hipMalloc(&r->d_state, sizeof(double) * state);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_inst, desc.data(), sizeof(RdvmInst) * desc.size(), hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_nodes, nodes.data(), sizeof(double) * nodes.size(), hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_tabs, tabs.data(), sizeof(double) * tabs.size(), hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(r->d_state, 0, sizeof(double) * state, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) {
+        lbm_status st = fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "reduced DVM set-up: %s", hipGetErrorString(e));
+        lbm_rdvm_free(r);
+        (void)hipGetLastError();
+        return st;
+    }
+    *out = r;
+    return LBM_OK;
+}
+
+lbm_status lbm_rdvm_reset(lbm_rdvm *r) {
+    if (!r) return fail(LBM_EINVAL, "reduced DVM is NULL");
+    HIP_TRY(hipMemsetAsync(r->d_state, 0, sizeof(double) * r->state_elems, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    r->nstep = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_rdvm_run(lbm_rdvm *r, int64_t steps, int32_t record_every, double *velocity, double *stress) {
+    if (!r) return fail(LBM_EINVAL, "reduced DVM is NULL");
+    if (steps < 0 || record_every < 0) return fail(LBM_EINVAL, "steps and record_every must be >= 0");
+    if (steps == 0) return LBM_OK;
+    const int64_t nrec64 = record_every > 0 ? steps / record_every : 0;
+    if (nrec64 > 0x7fffffff) return fail(LBM_EINVAL, "too many records");
+    const int32_t nrec = (int32_t)nrec64;
+    const size_t need = (size_t)r->count * 2 * (size_t)nrec;
+    if (need > r->log_cap) {
+        if (r->d_log) HIP_TRY(hipFree(r->d_log));
+        r->d_log = nullptr;
+        r->log_cap = 0;
+        HIP_TRY(hipMalloc(&r->d_log, sizeof(double) * need));
+        r->log_cap = need;
+        // each instance's records sit at log_off .. + 2 nrec; refresh the descriptors
+    }
+    for (int i = 0; i < r->count; ++i) r->desc[(size_t)i].log_off = (uint64_t)i * 2 * (uint64_t)nrec;
+    HIP_TRY(hipMemcpyAsync(r->d_inst, r->desc.data(), sizeof(RdvmInst) * r->desc.size(), hipMemcpyHostToDevice, r->stream));
+    RdvmArgs a{};
+    a.inst = r->d_inst;
+    a.nodes = r->d_nodes;
+    a.tabs = r->d_tabs;
+    a.state = r->d_state;
+    a.log = r->d_log;
+    a.step0 = r->nstep;
+    a.steps = steps;
+    a.record = nrec > 0 ? record_every : 0;
+    a.nrec = nrec;
+    HIP_TRY(launch_rdvm(a, (uint32_t)r->count, r->lds_bytes, r->stream));
+    r->nstep += steps;
+    if (nrec > 0 && (velocity || stress)) {
+        std::vector<double> h(need);
+        HIP_TRY(hipMemcpyAsync(h.data(), r->d_log, sizeof(double) * need, hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        for (int i = 0; i < r->count; ++i)
+            for (int32_t k = 0; k < nrec; ++k) {
+                if (velocity) velocity[(size_t)i * nrec + k] = h[(size_t)i * 2 * nrec + k];
+                if (stress) stress[(size_t)i * nrec + k] = h[(size_t)i * 2 * nrec + nrec + k];
+            }
+    } else {
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_rdvm_state(lbm_rdvm *r, int32_t index, double *g) {
+    if (!r || !g) return fail(LBM_EINVAL, "NULL argument");
+    if (index < 0 || index >= r->count) return fail(LBM_EINVAL, "instance %d out of range", index);
+    const RdvmInst &d = r->desc[(size_t)index];
+    HIP_TRY(hipMemcpyAsync(g, r->d_state + d.state_off, sizeof(double) * (size_t)d.M * d.nw, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_rdvm_info(const lbm_rdvm *r, int32_t index, double *dt, double *omega, int64_t *step) {
+    if (!r) return fail(LBM_EINVAL, "reduced DVM is NULL");
+    if (index < 0 || index >= r->count) return fail(LBM_EINVAL, "instance %d out of range", index);
+    if (dt) *dt = r->desc[(size_t)index].dt;
+    if (omega) *omega = r->desc[(size_t)index].omega;
+    if (step) *step = r->nstep;
+    return LBM_OK;
+}
+
+}  // extern "C"

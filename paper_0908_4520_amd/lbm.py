@@ -94,8 +94,21 @@ SIGNATURES = {
     "lbm_batch_set_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
+    "lbm_gauss_hermite": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
+    "lbm_rdvm_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_void_p]),
+    "lbm_rdvm_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbm_rdvm_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _D, _D]),
+    "lbm_rdvm_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D]),
+    "lbm_rdvm_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D, _D, _I64]),
+    "lbm_rdvm_free": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
+
+
+class lbm_rdvm_instance(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int32), ("cells", ctypes.c_int32), ("kn", ctypes.c_double),
+                ("amplitude", ctypes.c_double), ("frequency", ctypes.c_double)]
 
 
 def _load():
@@ -367,3 +380,57 @@ class Batch:
 
     def set_form(self, form: int, block: int):
         _check(_lib.lbm_batch_set_form(self._h, form, block))
+
+
+def lbm_gauss_hermite(n: int):
+    """(nodes, weights) of the library's n-point Gauss-Hermite rule (weights sum to 1)."""
+    x, w = np.zeros(n), np.zeros(n)
+    _check(_lib.lbm_gauss_hermite(n, _dp(x), _dp(w)))
+    return x, w
+
+
+class ReducedDVM:
+    """Owner of one lbm_rdvm*: instances (nodes, cells, kn, amplitude, frequency)."""
+
+    def __init__(self, instances, cfl: float = 0.5, stream=None):
+        arr = (lbm_rdvm_instance * len(instances))()
+        for i, (m, nw, kn, amp, freq) in enumerate(instances):
+            arr[i] = lbm_rdvm_instance(int(m), int(nw), float(kn), float(amp), float(freq))
+        self._inst = [tuple(x) for x in instances]
+        h = ctypes.c_void_p()
+        _check(_lib.lbm_rdvm_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(instances), cfl,
+                                    None if stream is None else ctypes.c_void_p(stream)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.lbm_rdvm_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self):
+        _check(_lib.lbm_rdvm_reset(self._h))
+
+    def run(self, steps: int, record_every: int = 0):
+        """Returns (velocity, stress) records of shape (count, steps // record_every)."""
+        n = len(self._inst)
+        nrec = steps // record_every if record_every > 0 else 0
+        vel, st = np.zeros((n, max(nrec, 1))), np.zeros((n, max(nrec, 1)))
+        _check(_lib.lbm_rdvm_run(self._h, steps, record_every, _dp(vel), _dp(st)))
+        return vel[:, :nrec], st[:, :nrec]
+
+    def state(self, index: int) -> np.ndarray:
+        m, nw = self._inst[index][0], self._inst[index][1]
+        g = np.zeros(m * nw)
+        _check(_lib.lbm_rdvm_state(self._h, index, _dp(g)))
+        return g.reshape(m, nw)
+
+    def info(self, index: int):
+        dt, om, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.lbm_rdvm_info(self._h, index, ctypes.byref(dt), ctypes.byref(om), ctypes.byref(n)))
+        return dt.value, om.value, n.value

@@ -135,3 +135,32 @@ def test_collisionless_tau_accepted_by_validation(lbm):
     with pytest.raises(lbm.LbmError) as e:
         lbm.Sim("D2Q9", 2, math.inf, (4, 4, 1))
     assert e.value.code in (lbm.LBM_EDEVICE, lbm.LBM_ENOMEM)
+
+
+def test_gauss_hermite_tables_agree_with_numpy(lbm):
+    from numpy.polynomial.hermite_e import hermegauss
+    assert ctypes.sizeof(lbm.lbm_rdvm_instance) == 32
+    for n in range(2, 65):
+        x, w = lbm.lbm_gauss_hermite(n)
+        xr, wr = hermegauss(n)
+        np.testing.assert_allclose(x, xr, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(w, wr / math.sqrt(2 * math.pi), rtol=1e-13, atol=0)
+        assert abs(w.sum() - 1.0) <= 1e-14
+    for n in (1, 65):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_gauss_hermite(n)
+
+
+BAD_RDVM = [((1, 16, 0.1, 1e-3, 0.0), "nodes"), ((65, 16, 0.1, 1e-3, 0.0), "nodes"),
+            ((8, 0, 0.1, 1e-3, 0.0), "cells"), ((8, 257, 0.1, 1e-3, 0.0), "cells"),
+            ((8, 16, 0.0, 1e-3, 0.0), "kn"),
+            ((8, 16, 0.1, float("nan"), 0.0), "kn")]
+
+
+@pytest.mark.parametrize("inst,msg", BAD_RDVM)
+def test_reduced_dvm_rejects_invalid_instances_without_device(lbm, inst, msg):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.ReducedDVM([(4, 8, 1.0, 0.0, 0.0), inst])
+    assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
+    with pytest.raises(lbm.LbmError):
+        lbm.ReducedDVM([(4, 8, 1.0, 0.0, 0.0)], cfl=1.5)

@@ -89,3 +89,18 @@ def test_linear_solution_converges_in_velocities():
     u20, _ = linmode.reduced_response(20, 0.5, 128, 1.0, 0.25)
     u40, _ = linmode.reduced_response(40, 0.5, 128, 1.0, 0.25)
     assert abs(u40 - u20) <= 1e-4 * abs(u40)
+
+
+@pytest.mark.parametrize("M,kn,phi", [(12, 0.3, 0.25), (7, math.inf, 0.0), (20, 0.02, 0.5)])
+def test_series_from_rest_is_the_linear_recursion(M, kn, phi):
+    nw, A = 40, 1e-3
+    r = reduced_dvm.ReducedDVM(M, nw, kn, A, phi)
+    u, s = [], []
+    for _ in range(30):
+        r.step(7)
+        a = r.amplitudes()
+        u.append(a[0])
+        s.append(a[1])
+    lu, ls = linmode.reduced_series(M, kn, nw, A, phi, 210, 7)
+    assert np.max(np.abs(np.array(u) - lu)) <= 1e-12 * np.max(np.abs(lu))
+    assert np.max(np.abs(np.array(s) - ls)) <= 1e-12 * np.max(np.abs(ls))
