@@ -9,11 +9,26 @@
 namespace lbm {
 
 constexpr int kRdvmMaxNodes = 64;    // velocities per instance
-constexpr int kRdvmBlock = 256;      // threads per workgroup = the largest N_w (one cell each)
+constexpr int kRdvmMaxCells = 256;   // N_w per instance
+constexpr int kRdvmBlock = 512;      // threads per workgroup
 constexpr int kRdvmMaxValues = 16384; // M * N_w: the state lives in LDS (128 KiB)
 
+// Threads per cell P (a power of two, P * N_w <= kRdvmBlock, P <= 64 so a cell's threads sit in
+// one wave); thread t serves cell t / P and the velocities k = t % P + q P.
+inline int rdvm_threads_per_cell(int nw) {
+    int P = 64;
+    while (P > 1 && P * nw > kRdvmBlock) P >>= 1;
+    return P;
+}
+// Velocities per thread, rounded up to a kernel variant: 4, 8, 16 or 32 (P >= 2, M <= 64).
+inline int rdvm_variant(int M, int nw) {
+    const int P = rdvm_threads_per_cell(nw), k = (M + P - 1) / P;
+    return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+}
+constexpr int kRdvmVariants = 4;
+
 struct RdvmInst {
-    int32_t M, nw;
+    int32_t M, nw, P;     // velocities, cells, threads per cell
     double dt, omega, amp, freq;
     uint32_t node_off;    // nodes: xi[M], w[M], alpha[M], beta[M] (Beam-Warming coefficients)
     uint32_t tab_off;     // tabs: cos(2 pi j / nw)[nw], then sin[nw]
@@ -33,8 +48,14 @@ struct RdvmArgs {
     int32_t nrec;         // records per instance in this launch
 };
 
-// One workgroup per instance; lds_bytes = 8 * (max M * N_w + 4).
-hipError_t launch_rdvm(const RdvmArgs &a, uint32_t count, size_t lds_bytes, hipStream_t s);
+// One workgroup per instance of the list `index` (count entries), all of kernel variant K;
+// lds_bytes = rdvm_lds_bytes(largest M * N_w, largest M).
+// LDS: the state, the coefficients, two sums per wave and the force time factor.
+inline size_t rdvm_lds_bytes(size_t values, int M) {
+    return sizeof(double) * (values + 4 * (size_t)M + 2 * (kRdvmBlock / 64) + 1);
+}
+hipError_t launch_rdvm(int K, const RdvmArgs &a, const int32_t *index, uint32_t count, size_t lds_bytes,
+                       hipStream_t s);
 hipError_t rdvm_allow_lds(size_t lds_bytes);
 
 }  // namespace lbm

@@ -10,91 +10,147 @@
 //   G~*_k = G~_k - omega (G~_k - u) + (1 - omega/2) dt F,   F = A cos(phi t) cos(2 pi j / N_w).
 // The recorded stress is sum_k w_k xi_k G_k = (1 - omega/2) sum_k w_k xi_k G~_k (pre-collision).
 //
-// One workgroup owns one instance for the whole launch: the state sits in LDS (M N_w doubles),
-// each thread owns one cell and keeps its M advected values in registers between the two
-// barriers of a step (read all neighbours, then write the relaxed values).  Nothing touches
-// HBM inside the step loop.
+// One workgroup of 512 threads owns one instance for the whole launch: the state sits in LDS
+// (M N_w doubles); P threads share a cell (P consecutive lanes of one wave), each advecting
+// and relaxing the velocities k = p, p + P, ... and keeping them, and their Beam-Warming
+// coefficients, in registers; u and the stress are summed over the P lanes by xor butterflies
+// (every lane of the group gets the same bits).  A step is: read the upwind neighbours of the
+// thread's velocities, barrier, write the relaxed values, barrier.  Nothing touches HBM inside
+// the step loop; thread 0 evaluates the force's time factor for the next step into LDS.
 #include "kernels_impl.h"
 #include "rdvm.h"
 
 namespace lbm {
 
-// Sum over the block in a fixed order (wave butterflies, then the waves in index order); every
-// thread gets the result.
-__device__ __forceinline__ double rdvm_block_sum(double x, double *red) {
-    const double s = wave_sum(x);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kRdvmBlock / 64; ++w) t += red[w];
-    return t;
-}
-
-__global__ __launch_bounds__(kRdvmBlock) void k_rdvm(RdvmArgs a) {
+// K velocities per thread at most; CREG: coefficients in registers (else read from LDS).
+template <int K, bool CREG>
+__global__ __launch_bounds__(kRdvmBlock) void k_rdvm(RdvmArgs a, const int32_t *index) {
     extern __shared__ double lds[];
-    const RdvmInst in = a.inst[blockIdx.x];
-    const int M = in.M, nw = in.nw, j = threadIdx.x;
+    const RdvmInst in = a.inst[index[blockIdx.x]];
+    const int M = in.M, nw = in.nw, P = in.P;
+    const int t = threadIdx.x, j = t / P, p = t % P;
     const bool own = j < nw;
-    double *G = lds;                          // [M][nw]
-    double *red = lds + (size_t)M * nw;       // [kRdvmBlock / 64]
+    double *G = lds;                               // [M][nw]
+    double *cst = lds + (size_t)M * nw;            // xi[M], w[M], alpha[M], beta[M]
+    double *red = cst + 4 * (size_t)M;             // [2 * kRdvmBlock / 64] per-wave record sums
+    double *tf = red + 2 * (kRdvmBlock / 64);      // force time factor of the coming step
     double *gst = a.state + in.state_off;
-    for (int i = threadIdx.x; i < M * nw; i += kRdvmBlock) G[i] = gst[i];
-    const double *xi = a.nodes + in.node_off, *w = xi + M, *al = w + M, *be = al + M;
+    for (int i = t; i < M * nw; i += kRdvmBlock) G[i] = gst[i];
+    for (int i = t; i < 4 * M; i += kRdvmBlock) cst[i] = a.nodes[in.node_off + i];
+    const int jc = own ? j : 0;
     const double cj = own ? a.tabs[in.tab_off + j] : 0.0;
     const double sj = own ? a.tabs[in.tab_off + nw + j] : 0.0;
-    const int jc = own ? j : 0;
     const int jm1 = (jc + nw - 1) % nw, jm2 = (jc + 2 * nw - 2) % nw;
     const int jp1 = (jc + 1) % nw, jp2 = (jc + 2) % nw;
     const double om = in.omega, kf = 1.0 - 0.5 * om;
+    if (t == 0) tf[0] = cos(in.freq * (double)(a.step0 + 1) * in.dt);
     __syncthreads();
+    // with CREG the thread's coefficients and upwind neighbours live in registers
+    double cx[CREG ? K : 1], cw[CREG ? K : 1], ca[CREG ? K : 1], cb[CREG ? K : 1];
+    int up1[CREG ? K : 1], up2[CREG ? K : 1];
+    if constexpr (CREG) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int k = p + q * P;
+            const bool v = k < M;
+            cx[q] = v ? cst[k] : 0.0;
+            cw[q] = v ? cst[M + k] : 0.0;
+            ca[q] = v ? cst[2 * M + k] : 0.0;
+            cb[q] = v ? cst[3 * M + k] : 0.0;
+            up1[q] = cx[q] > 0.0 ? jm1 : jp1;       // upwind neighbours
+            up2[q] = cx[q] > 0.0 ? jm2 : jp2;
+        }
+    }
+    int32_t to_rec = a.record, nrec = 0;             // steps to the next record, records done
     for (int64_t st = 0; st < a.steps; ++st) {
-        double g[kRdvmMaxNodes];
+        double g[K];
         double u = 0.0, sig = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRdvmMaxNodes; ++k) {
+        for (int q = 0; q < K; ++q) {
+            const int k = p + q * P;
             if (k < M) {
                 const double *row = G + (size_t)k * nw;
-                const bool up_left = xi[k] > 0.0;            // upwind cells j-1, j-2
-                const double f0 = row[jc];
-                const double f1 = row[up_left ? jm1 : jp1], f2 = row[up_left ? jm2 : jp2];
-                const double v = f0 - al[k] * (f0 - f1) + be[k] * (f1 - f2);
-                g[k] = v;
-                u += w[k] * v;
-                sig += w[k] * xi[k] * v;
+                double xk, wk, al, be;
+                int i1, i2;
+                if constexpr (CREG) {
+                    xk = cx[q], wk = cw[q], al = ca[q], be = cb[q], i1 = up1[q], i2 = up2[q];
+                } else {
+                    xk = cst[k], wk = cst[M + k], al = cst[2 * M + k], be = cst[3 * M + k];
+                    i1 = xk > 0.0 ? jm1 : jp1;
+                    i2 = xk > 0.0 ? jm2 : jp2;
+                }
+                const double f0 = row[jc], f1 = row[i1], f2 = row[i2];
+                const double v = f0 - al * (f0 - f1) + be * (f1 - f2);
+                g[q] = v;
+                u += wk * v;
+                sig += wk * xk * v;
             }
         }
-        __syncthreads();                                     // every neighbour read
-        const double t = (double)(a.step0 + st + 1) * in.dt;
-        const double dF = in.dt * in.amp * cos(in.freq * t) * cj;
+        for (int off = 1; off < P; off <<= 1) {      // sum over the cell's P lanes
+            u += __shfl_xor(u, off, 64);
+            sig += __shfl_xor(sig, off, 64);
+        }
+        __syncthreads();                             // every neighbour read
+        const double dF = in.dt * in.amp * tf[0] * cj;
         u += 0.5 * dF;
         if (own) {
 #pragma unroll
-            for (int k = 0; k < kRdvmMaxNodes; ++k)
-                if (k < M) G[(size_t)k * nw + j] = g[k] - om * (g[k] - u) + kf * dF;
-        }
-        __syncthreads();                                     // every cell relaxed
-        if (a.record > 0 && (st + 1) % a.record == 0) {
-            const double su = rdvm_block_sum(own ? u * cj : 0.0, red);
-            const double ss = rdvm_block_sum(own ? kf * sig * sj : 0.0, red);
-            if (threadIdx.x == 0) {
-                const int64_t r = (st + 1) / a.record - 1;
-                a.log[in.log_off + r] = 2.0 * su / (double)nw;
-                a.log[in.log_off + a.nrec + r] = 2.0 * ss / (double)nw;
+            for (int q = 0; q < K; ++q) {
+                const int k = p + q * P;
+                if (k < M) G[(size_t)k * nw + j] = g[q] - om * (g[q] - u) + kf * dF;
             }
         }
+        const bool rec = a.record > 0 && --to_rec == 0;
+        __syncthreads();                             // every cell relaxed, tf read
+        if (t == 0) tf[0] = cos(in.freq * (double)(a.step0 + st + 2) * in.dt);
+        if (rec) {
+            const bool lead = own && p == 0;
+            double su = wave_sum(lead ? u * cj : 0.0), ss = wave_sum(lead ? kf * sig * sj : 0.0);
+            if ((t & 63) == 0) {
+                red[2 * (t >> 6)] = su;
+                red[2 * (t >> 6) + 1] = ss;
+            }
+            __syncthreads();
+            if (t == 0) {
+                su = 0.0;
+                ss = 0.0;
+                for (int w = 0; w < kRdvmBlock / 64; ++w) {
+                    su += red[2 * w];
+                    ss += red[2 * w + 1];
+                }
+                a.log[in.log_off + nrec] = 2.0 * su / (double)nw;
+                a.log[in.log_off + a.nrec + nrec] = 2.0 * ss / (double)nw;
+            }
+            __syncthreads();                         // red free again
+            to_rec = a.record;
+            ++nrec;
+        }
     }
-    for (int i = threadIdx.x; i < M * nw; i += kRdvmBlock) gst[i] = G[i];
+    for (int i = t; i < M * nw; i += kRdvmBlock) gst[i] = G[i];
 }
 
 hipError_t rdvm_allow_lds(size_t lds_bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdvm), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes);
+    for (const void *f : {reinterpret_cast<const void *>(&k_rdvm<4, true>), reinterpret_cast<const void *>(&k_rdvm<8, true>),
+                          reinterpret_cast<const void *>(&k_rdvm<16, false>),
+                          reinterpret_cast<const void *>(&k_rdvm<32, false>)}) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_rdvm(const RdvmArgs &a, uint32_t count, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(k_rdvm, dim3(count), dim3(kRdvmBlock), lds_bytes, s, a);
+hipError_t launch_rdvm(int K, const RdvmArgs &a, const int32_t *index, uint32_t count, size_t lds_bytes,
+                       hipStream_t s) {
+    if (K == 4)
+        hipLaunchKernelGGL((k_rdvm<4, true>), dim3(count), dim3(kRdvmBlock), lds_bytes, s, a, index);
+    else if (K == 8)
+        hipLaunchKernelGGL((k_rdvm<8, true>), dim3(count), dim3(kRdvmBlock), lds_bytes, s, a, index);
+    else if (K == 16)
+        hipLaunchKernelGGL((k_rdvm<16, false>), dim3(count), dim3(kRdvmBlock), lds_bytes, s, a, index);
+    else if (K == 32)
+        hipLaunchKernelGGL((k_rdvm<32, false>), dim3(count), dim3(kRdvmBlock), lds_bytes, s, a, index);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -1283,6 +1283,8 @@ struct lbm_rdvm {
     std::vector<lbm_rdvm_instance> inst;
     std::vector<RdvmInst> desc;
     RdvmInst *d_inst = nullptr;
+    int32_t *d_index = nullptr;             // instance indices grouped by kernel variant
+    int group_first[kRdvmVariants + 1] = {};  // variant 4 << g: d_index[group_first[g] .. group_first[g+1])
     double *d_nodes = nullptr, *d_tabs = nullptr, *d_state = nullptr, *d_log = nullptr;
     size_t state_elems = 0, log_cap = 0, lds_bytes = 0;
     int64_t nstep = 0;
@@ -1303,7 +1305,8 @@ lbm_status lbm_gauss_hermite(int32_t n, double *nodes, double *weights) {
 void lbm_rdvm_free(lbm_rdvm *r) {
     if (!r) return;
     (void)hipStreamSynchronize(r->stream);
-    for (void *p : {(void *)r->d_inst, (void *)r->d_nodes, (void *)r->d_tabs, (void *)r->d_state, (void *)r->d_log})
+    for (void *p : {(void *)r->d_inst, (void *)r->d_index, (void *)r->d_nodes, (void *)r->d_tabs, (void *)r->d_state,
+                    (void *)r->d_log})
         if (p) (void)hipFree(p);
     delete r;
 }
@@ -1315,12 +1318,13 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
     std::vector<double> nodes, tabs;
     std::vector<RdvmInst> desc((size_t)count);
     size_t state = 0, maxv = 0;
+    int maxm = 0;
     for (int i = 0; i < count; ++i) {
         const lbm_rdvm_instance &q = inst[i];
         if (q.nodes < kGHMin || q.nodes > kRdvmMaxNodes)
             return fail(LBM_EINVAL, "instance %d: nodes must be in [%d, %d]", i, kGHMin, kRdvmMaxNodes);
-        if (q.cells < 1 || q.cells > kRdvmBlock)
-            return fail(LBM_EINVAL, "instance %d: cells must be in [1, %d]", i, kRdvmBlock);
+        if (q.cells < 1 || q.cells > kRdvmMaxCells)
+            return fail(LBM_EINVAL, "instance %d: cells must be in [1, %d]", i, kRdvmMaxCells);
         if ((size_t)q.nodes * (size_t)q.cells > (size_t)kRdvmMaxValues)
             return fail(LBM_EINVAL, "instance %d: nodes * cells exceeds %d", i, kRdvmMaxValues);
         if (!(q.kn > 0.0) || !isfinite(q.amplitude) || !isfinite(q.frequency))
@@ -1330,6 +1334,7 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
         RdvmInst &d = desc[(size_t)i];
         d.M = M;
         d.nw = nw;
+        d.P = rdvm_threads_per_cell(nw);
         d.dt = cfl * (2.0 * M_PI / (double)nw) / ximax;
         d.omega = isinf(q.kn) ? 0.0 : d.dt / (q.kn + 0.5 * d.dt);
         d.amp = q.amplitude;
@@ -1351,7 +1356,16 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
         d.state_off = state;
         state += (size_t)M * nw;
         maxv = std::max(maxv, (size_t)M * nw);
+        maxm = std::max(maxm, M);
     }
+    std::vector<int32_t> index;
+    int group_first[kRdvmVariants + 1];
+    for (int g = 0; g < kRdvmVariants; ++g) {
+        group_first[g] = (int)index.size();
+        for (int i = 0; i < count; ++i)
+            if (rdvm_variant(inst[i].nodes, inst[i].cells) == (4 << g)) index.push_back(i);
+    }
+    group_first[kRdvmVariants] = (int)index.size();
     lbm_rdvm *r = new lbm_rdvm();
     r->count = count;
     r->cfl = cfl;
@@ -1359,9 +1373,13 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
     r->inst.assign(inst, inst + count);
     r->desc = desc;
     r->state_elems = state;
-    r->lds_bytes = sizeof(double) * (maxv + kRdvmBlock / 64);
+    r->lds_bytes = rdvm_lds_bytes(maxv, maxm);
+    for (int g = 0; g <= kRdvmVariants; ++g) r->group_first[g] = group_first[g];
     hipError_t e = rdvm_allow_lds(r->lds_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->d_inst, sizeof(RdvmInst) * desc.size());
+    if (e == hipSuccess) e = hipMalloc(&r->d_index, sizeof(int32_t) * index.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->d_index, index.data(), sizeof(int32_t) * index.size(), hipMemcpyHostToDevice, r->stream);
     if (e == hipSuccess) e = hipMalloc(&r->d_nodes, sizeof(double) * nodes.size());
     if (e == hipSuccess) e = hipMalloc(&r->d_tabs, sizeof(double) * tabs.size());
     if (e == hipSuccess) e = hipMalloc(&r->d_state, sizeof(double) * state);
@@ -1416,7 +1434,10 @@ lbm_status lbm_rdvm_run(lbm_rdvm *r, int64_t steps, int32_t record_every, double
     a.steps = steps;
     a.record = nrec > 0 ? record_every : 0;
     a.nrec = nrec;
-    HIP_TRY(launch_rdvm(a, (uint32_t)r->count, r->lds_bytes, r->stream));
+    for (int g = 0; g < kRdvmVariants; ++g) {
+        const int n = r->group_first[g + 1] - r->group_first[g];
+        if (n > 0) HIP_TRY(launch_rdvm(4 << g, a, r->d_index + r->group_first[g], (uint32_t)n, r->lds_bytes, r->stream));
+    }
     r->nstep += steps;
     if (nrec > 0 && (velocity || stress)) {
         std::vector<double> h(need);
