@@ -51,9 +51,9 @@ def _template_args(name: str):
 
 
 def _nontemporal(name: str) -> bool:
-    """k_shift_rows<L, N, S, SR, BLOCK, NTS>: the last template argument."""
+    """k_shift_rows<L, N, S, SR, BLOCK, NTS, F>: the sixth template argument."""
     args = _template_args(name)
-    return "k_shift_rows<" in name and len(args) == 6 and args[5] == "true"
+    return "k_shift_rows<" in name and len(args) >= 6 and args[5] == "true"
 
 
 def read_trace(d: str):

@@ -14,8 +14,8 @@ TRACE_COLS = ["Kind", "Agent_Id", "Queue_Id", "Stream_Id", "Thread_Id", "Dispatc
 PMC_COLS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size", "Kernel_Id",
             "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
             "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
-K512 = "void lbm::k_shift_rows<lbm::D2Q37, 4, 2, false, 512, true>(lbm::StepArgs)"
-K256 = "void lbm::k_shift_rows<lbm::D2Q37, 4, 2, false, 256, false>(lbm::StepArgs)"
+K512 = "void lbm::k_shift_rows<lbm::D2Q37, 4, 2, false, 512, true, false>(lbm::StepArgs)"
+K256 = "void lbm::k_shift_rows<lbm::D2Q37, 4, 2, false, 256, false, false>(lbm::StepArgs)"
 COPY = counters.COPY_KERNEL
 
 
