@@ -187,8 +187,10 @@ lbm_status lbm_set_populations(lbm_sim *s, const double *f);
 lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
 
 /* Raw checkpoint of the stored state in its storage format (bit-exact restore):
- * lbm_state_bytes gives the size; save copies the current buffer to host memory, load copies
- * it back.  Together with lbm_step_count / lbm_set_step_count this resumes a run exactly. */
+ * lbm_state_bytes gives the size (Q ncell values); save copies the current buffer to host
+ * memory, load copies it back.  Together with lbm_step_count / lbm_set_step_count this resumes
+ * a run exactly.  Device layout: the Q populations of each grid row follow one another,
+ * population a of cell (x, y, z) at value ((z ny + y) Q + a) nx + x. */
 lbm_status lbm_state_bytes(const lbm_sim *s, int64_t *bytes);
 lbm_status lbm_save_state(lbm_sim *s, void *host, int64_t bytes);
 lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes);

@@ -15,12 +15,25 @@ namespace lbm {
 constexpr int kMaxQ = 40;       // largest Q of any supported set (D3Q39)
 constexpr int kBlock = 256;     // threads per workgroup of every step kernel
 
+// Where population i of cell (x, r) lives, r = y + ny z the row index: element
+// r * row + i * pop + x of a buffer.  A simulation stores the Q populations of each grid row
+// one after another (pop = nx, row = Q nx), so the rows a step reads lie close together in
+// memory; a batch instance stores one plane per population (pop = plane size, row = nx).
+struct Layout {
+    uint32_t nx, pop;
+    uint64_t row;
+    __host__ __device__ size_t at(int i, uint32_t cell) const {
+        const uint32_t r = cell / nx;
+        return (size_t)r * row + (size_t)i * pop + (cell - r * nx);
+    }
+};
+
 // Arguments shared by the step kernels (passed by value as kernel arguments).
 struct StepArgs {
     const void *fin;
     void *fout;
     int32_t nx, ny, nz;
-    uint32_t pstride;      // elements between consecutive population planes
+    Layout lay;
     uint32_t per_row;      // shift rows kernel: blocks per row; bw2: blocks per strip row
     uint32_t tile;         // shift rows kernel: block-size chunks per block; bw2: rows per strip
     uint32_t nblocks;      // grid size (1-D)
@@ -47,7 +60,7 @@ struct BWCoef {
 struct WaveArgs {
     void *f;
     int32_t nx, ny, nz;
-    uint32_t pstride;
+    Layout lay;
     int32_t wave_axis;
     double u0, rho_noise;
     uint64_t seed;
@@ -57,7 +70,7 @@ struct WaveArgs {
 struct DiagArgs {
     const void *f;
     int32_t nx, ny, nz;
-    uint32_t pstride;
+    Layout lay;
     int32_t wave_axis;
     const double *sin_tab, *cos_tab;
     double *partials;        // [nblocks][6]: sum u_x sin, sum u_x cos, sum d, sum j_x, j_y, j_z
@@ -72,15 +85,15 @@ using StepFn = hipError_t (*)(const StepArgs &, hipStream_t);
 using StepBW32 = hipError_t (*)(const StepArgs &, const BWCoef<float> &, hipStream_t);
 using StepBW64 = hipError_t (*)(const StepArgs &, const BWCoef<double> &, hipStream_t);
 using WaveFn = hipError_t (*)(const WaveArgs &, hipStream_t);
-using FieldsFn = hipError_t (*)(void *f, uint32_t pstride, uint32_t ncell, const double *rho,
+using FieldsFn = hipError_t (*)(void *f, const Layout &lay, uint32_t ncell, const double *rho,
                                 const double *u, hipStream_t);
-using DecodeFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, int a, double add,
+using DecodeFn = hipError_t (*)(const void *f, const Layout &lay, uint32_t ncell, int a, double add,
                                 double mul, double *out, hipStream_t);
-using EncodeFn = hipError_t (*)(void *f, uint32_t pstride, uint32_t ncell, int a, double add,
+using EncodeFn = hipError_t (*)(void *f, const Layout &lay, uint32_t ncell, int a, double add,
                                 double scale, const double *in, uint32_t sr_key, hipStream_t);
 using MomentsFn = hipError_t (*)(const DiagArgs &, double *rho, double *u, hipStream_t);
 using DiagFn = hipError_t (*)(const DiagArgs &, uint32_t nblocks, hipStream_t);
-using FiniteFn = hipError_t (*)(const void *f, uint32_t pstride, uint32_t ncell, int Q, int *flag,
+using FiniteFn = hipError_t (*)(const void *f, const Layout &lay, uint32_t ncell, int Q, int *flag,
                                 hipStream_t);
 
 // Everything for one (lattice, N, storage, rounding) combination.
@@ -88,6 +101,8 @@ struct KernelSet {
     int lattice, order, storage, sr;
     StepFn shift_rows[3];  // on-lattice shift, row tiles (needs nx, ny, nz >= R): 256 threads,
                            // 256 threads with non-temporal stores, 512 threads non-temporal
+    StepFn shift_rows4;    // on-lattice shift, 4 cells per thread, vector loads and stores, non-temporal
+                           // loads (FP32 storages, |c_x| <= 4, nx a multiple of 256; else null)
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
     StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
     StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision

@@ -50,115 +50,6 @@ __device__ __forceinline__ void store_stress(double *out, double ss, double sc) 
     }
 }
 
-// ---------------------------------------------------------------- exact shift, row tiles
-// Block = `tile` chunks of BLOCK consecutive cells of one row (y, z).  Thread pulls
-// f*_a(x - c_a) for every a, collides, and writes f*(x) to the other buffer.  Loads of one
-// population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned and,
-// with NTS, non-temporal: the output is not read again in this step, and streaming it past
-// the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
-// With F the collision adds the body force of the row and the stress sums are stored.
-template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
-__global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
-    using C = Codec<S>;
-    using raw = typename C::raw;
-    using T = typename C::T;
-    const uint32_t lb = xcd_tile(blockIdx.x, a.nblocks);
-    const uint32_t row = lb / a.per_row;
-    const uint32_t xb = lb - row * a.per_row;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
-    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
-    raw *__restrict__ fout = static_cast<raw *>(a.fout);
-    const size_t ps = a.pstride;
-    const T om = (T)a.omega;
-    const int jf = a.force_axis == 1 ? y : z;           // row index along the force axis
-    T Gx = T(0);
-    if constexpr (F) Gx = (T)(a.force_g * a.force_cos[jf]);
-    double sig_sum = 0.0;
-    for (uint32_t k = 0; k < a.tile; ++k) {
-        const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
-        if (x >= nx) break;
-        T v[L::Q];
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-            int ys = y - cy, zs = z - cz;
-            if constexpr (cy > 0) ys += (ys < 0) ? ny : 0;
-            if constexpr (cy < 0) ys -= (ys >= ny) ? ny : 0;
-            if constexpr (cz > 0) zs += (zs < 0) ? nz : 0;
-            if constexpr (cz < 0) zs -= (zs >= nz) ? nz : 0;
-            int xs = x - cx;
-            if constexpr (cx > 0) xs += (xs < 0) ? nx : 0;
-            if constexpr (cx < 0) xs -= (xs >= nx) ? nx : 0;
-            const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * (size_t)nx;
-            v[i] = C::dec(p[xs]);
-        });
-        if constexpr (F) {
-            T sig[2];
-            collide_impl<L, N, S, T, true>(v, om, Gx, sig);
-            sig_sum += (double)(a.force_axis == 1 ? sig[0] : sig[1]);
-        } else {
-            collide<L, N, S, T>(v, om);
-        }
-        const size_t o = (size_t)row * (size_t)nx + (size_t)x;
-        const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
-            if constexpr (NTS)
-                __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
-            else
-                fout[(size_t)i * ps + o] = r;
-        });
-    }
-    if constexpr (F)
-        if (a.stress) store_stress<BLOCK>(a.stress, sig_sum * a.force_sin[jf], sig_sum * a.force_cos[jf]);
-}
-
-// ---------------------------------------------------------------- exact shift, any grid
-template <class L, int N, int S, bool SR, bool F>
-__global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
-    using C = Codec<S>;
-    using raw = typename C::raw;
-    using T = typename C::T;
-    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
-    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
-    double ss = 0.0, sc = 0.0;
-    if (cell < ncell) {
-        const int nx = a.nx, ny = a.ny, nz = a.nz;
-        const int x = (int)(cell % (uint32_t)nx);
-        const uint32_t t = cell / (uint32_t)nx;
-        const int y = (int)(t % (uint32_t)ny), z = (int)(t / (uint32_t)ny);
-        const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
-        raw *__restrict__ fout = static_cast<raw *>(a.fout);
-        const size_t ps = a.pstride;
-        T v[L::Q];
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny), zs = imod(z - L::c[i][2], nz);
-            v[i] = C::dec(fin[(size_t)i * ps + (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs)]);
-        });
-        if constexpr (F) {
-            const int jf = a.force_axis == 1 ? y : z;
-            T sig[2];
-            collide_impl<L, N, S, T, true>(v, (T)a.omega, (T)(a.force_g * a.force_cos[jf]), sig);
-            const double sg = (double)(a.force_axis == 1 ? sig[0] : sig[1]);
-            ss = sg * a.force_sin[jf];
-            sc = sg * a.force_cos[jf];
-        } else {
-            collide<L, N, S, T>(v, (T)a.omega);
-        }
-        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            fout[(size_t)i * ps + cell] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
-        });
-    }
-    if constexpr (F)
-        if (a.stress) store_stress<kBlock>(a.stress, ss, sc);
-}
-
-// ---------------------------------------------------------------- Beam-Warming, 2-D
 // Cross-lane moves of one wave (DPP row/wave shifts, gfx9 family):
 //   shr: lane l takes lane l-1's value, lane 0 takes `old`;
 //   shl: lane l takes lane l+1's value, lane 63 takes `old`.
@@ -180,6 +71,215 @@ __device__ __forceinline__ double dpp_shl(double old, double v) {
     return __builtin_bit_cast(double, int2v{dpp_shl_i(o.x, x.x), dpp_shl_i(o.y, x.y)});
 }
 
+// ---------------------------------------------------------------- exact shift, row tiles
+// Block = `tile` chunks of BLOCK consecutive cells of one row (y, z).  Thread pulls
+// f*_a(x - c_a) for every a, collides, and writes f*(x) to the other buffer.  Loads of one
+// population by one wave cover 64 consecutive cells (256 B in FP32); stores are aligned and,
+// with NTS, non-temporal: the output is not read again in this step, and streaming it past
+// the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
+// With F the collision adds the body force of the row and the stress sums are stored.
+template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
+__global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    using T = typename C::T;
+    const uint32_t lb = xcd_tile(blockIdx.x, a.nblocks);
+    const uint32_t row = lb / a.per_row;
+    const uint32_t xb = lb - row * a.per_row;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+    raw *__restrict__ fout = static_cast<raw *>(a.fout);
+    const size_t ps = a.lay.pop, rs = a.lay.row;
+    const T om = (T)a.omega;
+    const int jf = a.force_axis == 1 ? y : z;           // row index along the force axis
+    T Gx = T(0);
+    if constexpr (F) Gx = (T)(a.force_g * a.force_cos[jf]);
+    double sig_sum = 0.0;
+    for (uint32_t k = 0; k < a.tile; ++k) {
+        const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
+        if (x >= nx) break;
+        T v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            int ys = y - cy, zs = z - cz;
+            if constexpr (cy > 0) ys += (ys < 0) ? ny : 0;
+            if constexpr (cy < 0) ys -= (ys >= ny) ? ny : 0;
+            if constexpr (cz > 0) zs += (zs < 0) ? nz : 0;
+            if constexpr (cz < 0) zs -= (zs >= nz) ? nz : 0;
+            int xs = x - cx;
+            if constexpr (cx > 0) xs += (xs < 0) ? nx : 0;
+            if constexpr (cx < 0) xs -= (xs >= nx) ? nx : 0;
+            const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * rs;
+            v[i] = C::dec(p[xs]);
+        });
+        if constexpr (F) {
+            T sig[2];
+            collide_impl<L, N, S, T, true>(v, om, Gx, sig);
+            sig_sum += (double)(a.force_axis == 1 ? sig[0] : sig[1]);
+        } else {
+            collide<L, N, S, T>(v, om);
+        }
+        const uint32_t cell = row * (uint32_t)nx + (uint32_t)x;
+        const size_t o = (size_t)row * rs + (size_t)x;
+        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            if constexpr (NTS)
+                __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
+            else
+                fout[(size_t)i * ps + o] = r;
+        });
+    }
+    if constexpr (F)
+        if (a.stress) store_stress<BLOCK>(a.stress, sig_sum * a.force_sin[jf], sig_sum * a.force_cos[jf]);
+}
+
+// ---------------------------------------------------------------- exact shift, 4 cells per thread
+// A wave owns 256 consecutive cells of a row, four per lane, loaded and stored as aligned
+// 4-element vectors (so every global access of a wave is one 1 KiB segment in FP32).  The
+// x-shift of population a by c_a (|c_a| <= 4) takes the missing elements from the neighbouring
+// lane by DPP lane moves; the lane at the wave's edge takes them from one 4-element load of the
+// neighbouring wave's cells, which every lane issues at the same address.  Needs nx a multiple
+// of 256 and rows aligned to 4 elements.  With NTL the loads are non-temporal.
+template <class L>
+constexpr int max_cx() {
+    int m = 0;
+    for (int i = 0; i < L::Q; ++i) m = L::c[i][0] > m ? L::c[i][0] : (-L::c[i][0] > m ? -L::c[i][0] : m);
+    return m;
+}
+
+template <class L, int N, int S, bool SR, bool NTL>
+__global__ __launch_bounds__(kBlock) void k_shift_rows4(StepArgs a) {
+    static_assert(max_cx<L>() <= 4, "x-shifts beyond one lane");
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    using T = typename C::T;
+    typedef raw rv4 __attribute__((ext_vector_type(4)));
+    const uint32_t lb = xcd_tile(blockIdx.x, a.nblocks);
+    const uint32_t row = lb / a.per_row;
+    const uint32_t xb = lb - row * a.per_row;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+    raw *__restrict__ fout = static_cast<raw *>(a.fout);
+    const size_t ps = a.lay.pop, rs = a.lay.row;
+    const T om = (T)a.omega;
+    for (uint32_t k = 0; k < a.tile; ++k) {
+        const int xw = (int)(((xb * a.tile + k) * (kBlock / 64) + wv) * 256);   // the wave's first cell
+        if (xw >= nx) break;                                                     // whole wave
+        const int x0 = xw + 4 * lane;
+        T v[4][L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            int ys = y - cy, zs = z - cz;
+            if constexpr (cy > 0) ys += (ys < 0) ? ny : 0;
+            if constexpr (cy < 0) ys -= (ys >= ny) ? ny : 0;
+            if constexpr (cz > 0) zs += (zs < 0) ? nz : 0;
+            if constexpr (cz < 0) zs -= (zs >= nz) ? nz : 0;
+            const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * rs;
+            rv4 ar;
+            if constexpr (NTL)
+                ar = __builtin_nontemporal_load(reinterpret_cast<const rv4 *>(p + x0));
+            else
+                ar = *reinterpret_cast<const rv4 *>(p + x0);
+            const T A[4] = {C::dec(ar.x), C::dec(ar.y), C::dec(ar.z), C::dec(ar.w)};
+            if constexpr (cx == 0) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v[m][i] = A[m];
+            } else if constexpr (cx > 0) {              // element m comes from cell x0 + m - cx
+                int hx = xw - 4;
+                hx += hx < 0 ? nx : 0;
+                const rv4 hr = *reinterpret_cast<const rv4 *>(p + hx);
+                const T H[4] = {C::dec(hr.x), C::dec(hr.y), C::dec(hr.z), C::dec(hr.w)};
+                T left[4];
+#pragma unroll
+                for (int m = 4 - cx; m < 4; ++m) left[m] = dpp_shr(H[m], A[m]);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v[m][i] = (m >= cx) ? A[m >= cx ? m - cx : 0] : left[m < cx ? 4 + m - cx : 0];
+            } else {
+                constexpr int c = -cx;
+                int hx = xw + 256;
+                hx -= hx >= nx ? nx : 0;
+                const rv4 hr = *reinterpret_cast<const rv4 *>(p + hx);
+                const T H[4] = {C::dec(hr.x), C::dec(hr.y), C::dec(hr.z), C::dec(hr.w)};
+                T right[4];
+#pragma unroll
+                for (int m = 0; m < c; ++m) right[m] = dpp_shl(H[m], A[m]);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v[m][i] = (m + c <= 3) ? A[m + c <= 3 ? m + c : 0] : right[m + c > 3 ? m + c - 4 : 0];
+            }
+        });
+#pragma unroll
+        for (int m = 0; m < 4; ++m) collide<L, N, S, T>(v[m], om);
+        const uint32_t cell = row * (uint32_t)nx + (uint32_t)x0;
+        const size_t o = (size_t)row * rs + (size_t)x0;
+        uint32_t h[4] = {0u, 0u, 0u, 0u};
+        if constexpr (SR) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) h[m] = mix32((cell + (uint32_t)m) ^ a.sr_key);
+        }
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            rv4 r;
+            r.x = C::template enc<SR>(v[0][i], SR ? pop_bits(h[0], i) : 0u);
+            r.y = C::template enc<SR>(v[1][i], SR ? pop_bits(h[1], i) : 0u);
+            r.z = C::template enc<SR>(v[2][i], SR ? pop_bits(h[2], i) : 0u);
+            r.w = C::template enc<SR>(v[3][i], SR ? pop_bits(h[3], i) : 0u);
+            __builtin_nontemporal_store(r, reinterpret_cast<rv4 *>(fout + (size_t)i * ps + o));
+        });
+    }
+}
+
+// ---------------------------------------------------------------- exact shift, any grid
+template <class L, int N, int S, bool SR, bool F>
+__global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
+    using C = Codec<S>;
+    using raw = typename C::raw;
+    using T = typename C::T;
+    const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    double ss = 0.0, sc = 0.0;
+    if (cell < ncell) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(cell % (uint32_t)nx);
+        const uint32_t t = cell / (uint32_t)nx;
+        const int y = (int)(t % (uint32_t)ny), z = (int)(t / (uint32_t)ny);
+        const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
+        raw *__restrict__ fout = static_cast<raw *>(a.fout);
+        const size_t ps = a.lay.pop, rs = a.lay.row;
+        T v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny), zs = imod(z - L::c[i][2], nz);
+            v[i] = C::dec(fin[(size_t)i * ps + (size_t)xs + rs * ((size_t)ys + (size_t)ny * zs)]);
+        });
+        if constexpr (F) {
+            const int jf = a.force_axis == 1 ? y : z;
+            T sig[2];
+            collide_impl<L, N, S, T, true>(v, (T)a.omega, (T)(a.force_g * a.force_cos[jf]), sig);
+            const double sg = (double)(a.force_axis == 1 ? sig[0] : sig[1]);
+            ss = sg * a.force_sin[jf];
+            sc = sg * a.force_cos[jf];
+        } else {
+            collide<L, N, S, T>(v, (T)a.omega);
+        }
+        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+        const size_t o = (size_t)t * rs + (size_t)x;
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+        });
+    }
+    if constexpr (F)
+        if (a.stress) store_stress<kBlock>(a.stress, ss, sc);
+}
+
+// ---------------------------------------------------------------- Beam-Warming, 2-D
 // Thread = one column x walking a strip of `tile` rows; a wave owns 64 consecutive
 // (aligned) columns.  For each population it keeps the x-advected values of the two
 // upwind rows in registers (sliding window over y).  The x-neighbours x - s, x - 2s come
@@ -213,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     const int y1 = min(y0 + (int)a.tile, ny);
     const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
     raw *__restrict__ fout = static_cast<raw *>(a.fout);
-    const size_t ps = a.pstride;
-    auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * (size_t)nx; };
+    const size_t ps = a.lay.pop;
+    auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * a.lay.row; };
     auto xadv = [&](auto I, size_t roff) -> T {
         constexpr int i = decltype(I)::value;
         const raw *p = fin + (size_t)i * ps + roff;
@@ -276,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
         }
         if (owner) {
             const size_t o = r0 + (size_t)xo;
-            const uint32_t h = SR ? mix32((uint32_t)o ^ a.sr_key) : 0u;
+            const uint32_t h = SR ? mix32((uint32_t)(y * nx + xo) ^ a.sr_key) : 0u;
             static_for<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
@@ -316,12 +416,12 @@ __global__ __launch_bounds__(kBlock) void k_init_wave(WaveArgs a) {
     raw *f = static_cast<raw *>(a.f);
     static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        f[(size_t)i * a.pstride + cell] = C::template enc<false>((typename C::T)v[i], 0u);
+        f[a.lay.at(i, cell)] = C::template enc<false>((typename C::T)v[i], 0u);
     });
 }
 
 template <class L, int N, int S>
-__global__ __launch_bounds__(kBlock) void k_init_fields(void *fv, uint32_t ps, uint32_t ncell,
+__global__ __launch_bounds__(kBlock) void k_init_fields(void *fv, Layout lay, uint32_t ncell,
                                                         const double *rho, const double *u) {
     using C = Codec<S>;
     using raw = typename C::raw;
@@ -332,30 +432,30 @@ __global__ __launch_bounds__(kBlock) void k_init_fields(void *fv, uint32_t ps, u
     raw *f = static_cast<raw *>(fv);
     static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        f[(size_t)i * ps + cell] = C::template enc<false>((typename C::T)v[i], 0u);
+        f[lay.at(i, cell)] = C::template enc<false>((typename C::T)v[i], 0u);
     });
 }
 
 // ---------------------------------------------------------------- codec kernels
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_decode(const void *fv, uint32_t ps, uint32_t ncell, int a,
+__global__ __launch_bounds__(kBlock) void k_decode(const void *fv, Layout lay, uint32_t ncell, int a,
                                                    double add, double mul, double *out) {
     using C = Codec<S>;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= ncell) return;
     const auto *f = static_cast<const typename C::raw *>(fv);
-    out[cell] = add + mul * C::dec64(f[(size_t)a * ps + cell]);
+    out[cell] = add + mul * C::dec64(f[lay.at(a, cell)]);
 }
 
 template <int S, bool SR>
-__global__ __launch_bounds__(kBlock) void k_encode(void *fv, uint32_t ps, uint32_t ncell, int a, double add,
+__global__ __launch_bounds__(kBlock) void k_encode(void *fv, Layout lay, uint32_t ncell, int a, double add,
                                                    double scale, const double *in, uint32_t key) {
     using C = Codec<S>;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= ncell) return;
     auto *f = static_cast<typename C::raw *>(fv);
     const double v = (in[cell] - add) * scale;
-    f[(size_t)a * ps + cell] = C::template enc<SR>((typename C::T)v, SR ? pop_bits(mix32(cell ^ key), a) : 0u);
+    f[lay.at(a, cell)] = C::template enc<SR>((typename C::T)v, SR ? pop_bits(mix32(cell ^ key), a) : 0u);
 }
 
 // Index of a cell along the force axis.
@@ -375,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(DiagArgs a, double *rho, dou
     double v[L::Q];
     static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        v[i] = C::dec64(f[(size_t)i * a.pstride + cell]);
+        v[i] = C::dec64(f[a.lay.at(i, cell)]);
     });
     const Moments<double> m = project<L, S>(v);
     const double r = C::dev ? 1.0 + m.d : m.d;
@@ -400,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a) {
         double v[L::Q];
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            v[i] = C::dec64(f[(size_t)i * a.pstride + cell]);
+            v[i] = C::dec64(f[a.lay.at(i, cell)]);
         });
         const Moments<double> m = project<L, S>(v);
         const double r = C::dev ? 1.0 + m.d : m.d;
@@ -435,13 +535,13 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a) {
 }
 
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_finite(const void *fv, uint32_t ps, uint32_t ncell, int Q,
+__global__ __launch_bounds__(kBlock) void k_finite(const void *fv, Layout lay, uint32_t ncell, int Q,
                                                    int *flag) {
     using C = Codec<S>;
     const auto *f = static_cast<const typename C::raw *>(fv);
     bool bad = false;
     for (uint32_t cell = blockIdx.x * kBlock + threadIdx.x; cell < ncell; cell += gridDim.x * kBlock)
-        for (int i = 0; i < Q; ++i) bad |= !isfinite((double)C::dec(f[(size_t)i * ps + cell]));
+        for (int i = 0; i < Q; ++i) bad |= !isfinite((double)C::dec(f[lay.at(i, cell)]));
     if (bad) atomicOr(flag, 1);
 }
 
@@ -451,6 +551,11 @@ inline uint32_t blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
 template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
 hipError_t launch_shift_rows(const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_shift_rows<L, N, S, SR, BLOCK, NTS, F>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+template <class L, int N, int S, bool SR, bool NTL>
+hipError_t launch_shift_rows4(const StepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_shift_rows4<L, N, S, SR, NTL>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 template <class L, int N, int S, bool SR, bool F>
@@ -470,21 +575,21 @@ hipError_t launch_init_wave(const WaveArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 template <class L, int N, int S>
-hipError_t launch_init_fields(void *f, uint32_t ps, uint32_t ncell, const double *rho, const double *u,
+hipError_t launch_init_fields(void *f, const Layout &lay, uint32_t ncell, const double *rho, const double *u,
                               hipStream_t s) {
-    hipLaunchKernelGGL((k_init_fields<L, N, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, rho, u);
+    hipLaunchKernelGGL((k_init_fields<L, N, S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, lay, ncell, rho, u);
     return hipGetLastError();
 }
 template <int S>
-hipError_t launch_decode(const void *f, uint32_t ps, uint32_t ncell, int a, double add, double mul, double *out,
+hipError_t launch_decode(const void *f, const Layout &lay, uint32_t ncell, int a, double add, double mul, double *out,
                          hipStream_t s) {
-    hipLaunchKernelGGL((k_decode<S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, a, add, mul, out);
+    hipLaunchKernelGGL((k_decode<S>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, lay, ncell, a, add, mul, out);
     return hipGetLastError();
 }
 template <int S, bool SR>
-hipError_t launch_encode(void *f, uint32_t ps, uint32_t ncell, int a, double add, double scale, const double *in,
+hipError_t launch_encode(void *f, const Layout &lay, uint32_t ncell, int a, double add, double scale, const double *in,
                          uint32_t key, hipStream_t s) {
-    hipLaunchKernelGGL((k_encode<S, SR>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, ps, ncell, a, add, scale,
+    hipLaunchKernelGGL((k_encode<S, SR>), dim3(blocks_for(ncell)), dim3(kBlock), 0, s, f, lay, ncell, a, add, scale,
                        in, key);
     return hipGetLastError();
 }
@@ -500,10 +605,10 @@ hipError_t launch_diag(const DiagArgs &a, uint32_t nblocks, hipStream_t s) {
     return hipGetLastError();
 }
 template <int S>
-hipError_t launch_finite(const void *f, uint32_t ps, uint32_t ncell, int Q, int *flag, hipStream_t s) {
+hipError_t launch_finite(const void *f, const Layout &lay, uint32_t ncell, int Q, int *flag, hipStream_t s) {
     uint32_t nb = blocks_for(ncell);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL((k_finite<S>), dim3(nb), dim3(kBlock), 0, s, f, ps, ncell, Q, flag);
+    hipLaunchKernelGGL((k_finite<S>), dim3(nb), dim3(kBlock), 0, s, f, lay, ncell, Q, flag);
     return hipGetLastError();
 }
 
@@ -521,6 +626,8 @@ KernelSet make_set() {
         k.shift_rows[2] = &launch_shift_rows<L, N, S, SR, 512, true, false>;
         k.shift_cells = &launch_shift_cells<L, N, S, SR, false>;
         k.shift_rows_forced = &launch_shift_rows<L, N, S, SR, 256, false, true>;
+        if constexpr (max_cx<L>() <= 4 && (S == ST_FP32 || S == ST_FP32_DEV))
+            k.shift_rows4 = &launch_shift_rows4<L, N, S, SR, true>;
         k.shift_cells_forced = &launch_shift_cells<L, N, S, SR, true>;
     } else if constexpr (L::D == 2) {
         if constexpr (S == ST_FP64) {

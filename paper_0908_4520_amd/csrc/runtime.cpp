@@ -104,13 +104,16 @@ uint64_t splitmix64(uint64_t x) {
 }
 
 // Step-kernel tile choices.  Shift: kernel variant (0: 256 threads, 1: 256 threads with
-// non-temporal stores, 2: 512 threads with non-temporal stores) and chunks per block.
+// non-temporal stores, 2: 512 threads with non-temporal stores, 3: 256 threads x 4 cells per
+// thread with vector accesses) and chunks per block (of block threads x cells per thread).
 // Beam-Warming: rows per strip.
 struct ShiftTile {
     int variant, block, chunks;
 };
 const ShiftTile kShiftTiles[] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256, 8}, {2, 512, 4},
-                                 {2, 512, 2}, {2, 512, 1}, {1, 256, 4}, {1, 256, 8}};
+                                 {2, 512, 2}, {2, 512, 1}, {1, 256, 4}, {1, 256, 8}, {3, 256, 1},
+                                 {3, 256, 2}};
+constexpr int kPlainShiftTiles = 9;   // without the vector tiles
 const int kBWTiles[] = {16, 32, 8, 4, 64};
 
 }  // namespace
@@ -121,7 +124,7 @@ struct lbm_sim {
     double tau = 0, omega = 0;
     lbm_grid g{};
     size_t ncell = 0;
-    uint32_t pstride = 0;
+    Layout lay{};              // row-interleaved: the Q populations of each row one after another
     lbm_opts o{};
     lbm_move move = LBM_MOVE_AUTO;
     int esize = 0;
@@ -167,7 +170,7 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     a.nx = s->g.nx;
     a.ny = s->g.ny;
     a.nz = s->g.nz;
-    a.pstride = s->pstride;
+    a.lay = s->lay;
     a.omega = s->omega;
     a.sr_key = (uint32_t)splitmix64(s->o.sr_seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(s->nstep + 1)));
     const uint32_t nx = (uint32_t)s->g.nx;
@@ -178,7 +181,7 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
         a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
     } else if (s->rows_ok) {
         const ShiftTile &t = kShiftTiles[tile_index];
-        const uint32_t cpt = (uint32_t)t.chunks, blk = (uint32_t)t.block;
+        const uint32_t cpt = (uint32_t)t.chunks, blk = (uint32_t)t.block * (t.variant == 3 ? 4u : 1u);
         a.tile = cpt;
         a.per_row = (nx + blk * cpt - 1) / (blk * cpt);
         a.nblocks = a.per_row * (uint32_t)s->g.ny * (uint32_t)s->g.nz;
@@ -213,15 +216,23 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
     }
     if (s->move == LBM_MOVE_BW2)
         return s->o.storage == LBM_FP64 ? k->bw2_f64(a, s->bwd, s->stream) : k->bw2_f32(a, s->bwf, s->stream);
-    return s->rows_ok ? k->shift_rows[kShiftTiles[tile_index].variant](a, s->stream) : k->shift_cells(a, s->stream);
+    if (!s->rows_ok) return k->shift_cells(a, s->stream);
+    const int v = kShiftTiles[tile_index].variant;
+    return v == 3 ? k->shift_rows4(a, s->stream) : k->shift_rows[v](a, s->stream);
 }
 
 // The forced row kernel exists in the plain 256-thread form only: the first four shift tiles.
 constexpr int kForcedShiftTiles = 4;
 
+// The vector tiles need their kernel (FP32 storages, |c_x| <= 4) and whole 256-cell waves.
+bool vector_tiles_ok(const lbm_sim *s) { return s->ks->shift_rows4 != nullptr && s->g.nx % 256 == 0; }
+
 int tile_count(const lbm_sim *s) {
     if (s->move == LBM_MOVE_BW2) return (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
-    if (s->rows_ok) return s->forced ? kForcedShiftTiles : (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]);
+    if (s->rows_ok) {
+        if (s->forced) return kForcedShiftTiles;
+        return vector_tiles_ok(s) ? (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]) : kPlainShiftTiles;
+    }
     return 1;
 }
 
@@ -259,7 +270,7 @@ lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
     a.nx = s->g.nx;
     a.ny = s->g.ny;
     a.nz = s->g.nz;
-    a.pstride = s->pstride;
+    a.lay = s->lay;
     a.wave_axis = axis;
     const int nw = axis == 1 ? s->g.ny : s->g.nz;
     a.sin_tab = s->d_tab;
@@ -360,7 +371,7 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     s->omega = isinf(tau) ? 0.0 : 1.0 / tau;
     s->g = g;
     s->ncell = (size_t)ncell;
-    s->pstride = (uint32_t)((ncell + 63) / 64 * 64);
+    s->lay = Layout{(uint32_t)g.nx, (uint32_t)g.nx, (uint64_t)L->Q * (uint64_t)g.nx};
     s->o = o;
     s->move = move;
     s->esize = elem_size(o.storage);
@@ -382,7 +393,7 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
             }
     }
     s->diag_blocks = (uint32_t)std::min<size_t>((s->ncell + kBlock - 1) / kBlock, 2048);
-    const size_t bytes = (size_t)L->Q * s->pstride * (size_t)s->esize;
+    const size_t bytes = (size_t)L->Q * s->ncell * (size_t)s->esize;
     hipError_t e = hipMalloc(&s->buf[0], bytes);
     if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
     if (e == hipSuccess) e = hipMalloc(&s->d_partials, sizeof(double) * 6 * s->diag_blocks);
@@ -437,7 +448,7 @@ lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double r
     a.nx = s->g.nx;
     a.ny = s->g.ny;
     a.nz = s->g.nz;
-    a.pstride = s->pstride;
+    a.lay = s->lay;
     a.wave_axis = wave_axis;
     a.u0 = u0;
     a.rho_noise = rho_noise;
@@ -457,7 +468,7 @@ lbm_status lbm_init_equilibrium(lbm_sim *s, const double *rho, const double *u) 
     HIP_TRY(hipMalloc(&d, sizeof(double) * n * (1 + D)));
     hipError_t e = hipMemcpyAsync(d, rho, sizeof(double) * n, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d + n, u, sizeof(double) * n * D, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = s->ks->init_fields(s->buf[0], s->pstride, (uint32_t)n, d, d + n, s->stream);
+    if (e == hipSuccess) e = s->ks->init_fields(s->buf[0], s->lay, (uint32_t)n, d, d + n, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     HIP_TRY(e);
@@ -477,7 +488,7 @@ lbm_status lbm_step(lbm_sim *s, int64_t n) {
         s->stress_valid = s->forced;
         if (s->o.check_every > 0 && s->nstep % s->o.check_every == 0) {
             HIP_TRY(fill_zero(s->d_flag, 1, s->stream));
-            HIP_TRY(s->ks->finite(s->buf[s->cur], s->pstride, (uint32_t)s->ncell, s->L->Q, s->d_flag, s->stream));
+            HIP_TRY(s->ks->finite(s->buf[s->cur], s->lay, (uint32_t)s->ncell, s->L->Q, s->d_flag, s->stream));
             int flag = 0;
             HIP_TRY(hipMemcpyAsync(&flag, s->d_flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
             HIP_TRY(hipStreamSynchronize(s->stream));
@@ -497,7 +508,7 @@ lbm_status lbm_moments(lbm_sim *s, double *rho, double *u) {
     a.nx = s->g.nx;
     a.ny = s->g.ny;
     a.nz = s->g.nz;
-    a.pstride = s->pstride;
+    a.lay = s->lay;
     a.half_g = 0.5 * force_g_at(s, s->nstep);
     a.force_cos = s->d_ftab;
     a.force_axis = s->f_axis;
@@ -543,7 +554,7 @@ lbm_status lbm_get_populations(lbm_sim *s, double *f) {
     for (int a = 0; a < s->L->Q && e == hipSuccess; ++a) {
         const double add = is_dev(s->o.storage) ? s->L->w[a] : 0.0;
         const double mul = is_scaled(s->o.storage) ? s->L->w[a] : 1.0;
-        e = s->ks->decode(s->buf[s->cur], s->pstride, (uint32_t)n, a, add, mul, d, s->stream);
+        e = s->ks->decode(s->buf[s->cur], s->lay, (uint32_t)n, a, add, mul, d, s->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(f + (size_t)a * n, d, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     }
@@ -563,7 +574,7 @@ lbm_status lbm_set_populations(lbm_sim *s, const double *f) {
         const double add = is_dev(s->o.storage) ? s->L->w[a] : 0.0;
         const double scale = is_scaled(s->o.storage) ? 1.0 / s->L->w[a] : 1.0;
         e = hipMemcpyAsync(d, f + (size_t)a * n, sizeof(double) * n, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = s->ks->encode(s->buf[s->cur], s->pstride, (uint32_t)n, a, add, scale, d, key, s->stream);
+        if (e == hipSuccess) e = s->ks->encode(s->buf[s->cur], s->lay, (uint32_t)n, a, add, scale, d, key, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     }
     (void)hipFree(d);
@@ -581,7 +592,7 @@ lbm_status lbm_set_step_count(lbm_sim *s, int64_t n) {
 
 lbm_status lbm_state_bytes(const lbm_sim *s, int64_t *bytes) {
     if (!s || !bytes) return fail(LBM_EINVAL, "NULL argument");
-    *bytes = (int64_t)s->L->Q * (int64_t)s->pstride * s->esize;
+    *bytes = (int64_t)s->L->Q * (int64_t)s->ncell * s->esize;
     return LBM_OK;
 }
 
@@ -747,7 +758,7 @@ lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads,
     const StepArgs a = step_args(s, s->buf[0], s->buf[1], tile);
     const bool rows = s->move != LBM_MOVE_BW2 && s->rows_ok;
     if (block_threads) *block_threads = rows ? kShiftTiles[tile].block : kBlock;
-    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile;
+    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile * (rows && kShiftTiles[tile].variant == 3 ? 4 : 1);
     if (blocks) *blocks = (int64_t)a.nblocks;
     if (nontemporal) *nontemporal = rows && kShiftTiles[tile].variant != 0;
     return LBM_OK;
@@ -756,7 +767,7 @@ lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads,
 lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile, double *best_ms) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
-    const size_t bytes = (size_t)s->L->Q * s->pstride * (size_t)s->esize;
+    const size_t bytes = (size_t)s->L->Q * s->ncell * (size_t)s->esize;
     void *scratch[2] = {nullptr, nullptr};
     HIP_TRY(hipMalloc(&scratch[0], bytes));
     hipError_t e = hipMalloc(&scratch[1], bytes);
@@ -856,7 +867,7 @@ lbm_status batch_init_states(lbm_batch *b) {
         a.nx = d.nx;
         a.ny = d.ny;
         a.nz = 1;
-        a.pstride = d.pstride;
+        a.lay = Layout{(uint32_t)d.nx, d.pstride, (uint64_t)d.nx};   // one plane per population
         a.wave_axis = 1;
         a.u0 = b->inst[i].u0;
         a.rho_noise = 0.0;
@@ -1187,7 +1198,7 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
     hipError_t e = hipSuccess;
     for (int a = 0; a < L->Q && e == hipSuccess; ++a) {
         const double add = is_dev(b->storage) ? L->w[a] : 0.0;
-        e = b->ks[index]->decode(base, d.pstride, d.ncell, a, add, 1.0, t, b->stream);
+        e = b->ks[index]->decode(base, Layout{(uint32_t)d.nx, d.pstride, (uint64_t)d.nx}, d.ncell, a, add, 1.0, t, b->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(f + (size_t)a * d.ncell, t, sizeof(double) * d.ncell, hipMemcpyDeviceToHost, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     }

@@ -155,9 +155,10 @@ def test_collisionless_shift_bit_exact(lattice, grid, storage):
     dt = {8: np.uint64, 4: np.uint32, 2: np.uint16}[esize]
     ncell = grid[0] * grid[1] * grid[2]
     Q = vs_c.shape[0]
-    ps = raw0.size // esize // Q
-    a0 = raw0.view(dt).reshape(Q, ps)[:, :ncell].reshape(Q, grid[2], grid[1], grid[0])
-    a1 = raw.view(dt).reshape(Q, ps)[:, :ncell].reshape(Q, grid[2], grid[1], grid[0])
+    assert raw0.size == esize * Q * ncell
+    # raw layout: the Q populations of each row (y, z) one after another
+    a0 = raw0.view(dt).reshape(grid[2], grid[1], Q, grid[0]).transpose(2, 0, 1, 3)
+    a1 = raw.view(dt).reshape(grid[2], grid[1], Q, grid[0]).transpose(2, 0, 1, 3)
     for a in range(Q):
         c = list(vs_c[a]) + [0] * (3 - D)
         moved = np.roll(a0[a], (n * c[2], n * c[1], n * c[0]), axis=(0, 1, 2))
@@ -227,9 +228,46 @@ def test_mass_momentum_conservation_gpu():
     assert np.max(np.abs(p1 - p0)) <= 1e-13 * m0
 
 
+VECTOR_CASES = [("D2Q37", 4, (512, 9, 1), "fp32_dev"), ("D2Q37", 2, (256, 7, 1), "fp32"),
+                ("D2Q9", 2, (768, 5, 1), "fp32_dev"), ("D3Q39", 4, (256, 4, 7), "fp32_dev"),
+                ("D2Q16-CK", 3, (512, 9, 1), "fp32_dev"), ("D2Q17", 3, (256, 8, 1), "fp32"),
+                ("D2Q21", 3, (256, 8, 1), "fp32_dev")]
+
+
+@pytest.mark.parametrize("lattice,N,grid,storage", VECTOR_CASES)
+def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage):
+    """Every tile, including the two 4-cells-per-thread tiles (nx a multiple of 256, |c_x| <= 4,
+    FP32 storages): against the oracle, and bit for bit against tile 0 (same arithmetic)."""
+    lbm = need_gpu()
+    vs = OL.get(lattice)
+    axis = 2 if vs.D == 3 else 1
+    tau = 0.93
+    r = ob.BGK(lattice, N, tau, grid)
+    r.set_shear_wave(1e-3, axis, rho_noise=1e-6, seed=3)
+    r.step(5)
+    p = perm(lattice)
+    with lbm.Sim(lattice, N, tau, grid, storage=storage) as s:
+        assert s.tile_count() == 11
+        ref = None
+        for t in range(s.tile_count()):
+            s.set_tile(t)
+            s.set_shear_wave(1e-3, axis, rho_noise=1e-6, seed=3)
+            s.step(5)
+            st = s.save_state()
+            err = rel_err(s.get_populations(), r.f[p])
+            say(f"{lattice} {grid} {storage} tile {t} {s.tile_info(t)}: {err:.2e}")
+            assert err <= 1e-5
+            if ref is None:
+                ref = st
+            else:
+                assert np.array_equal(st, ref)
+
+
 @pytest.mark.parametrize("lattice,grid,storage", [("D2Q37", (600, 40, 1), "fp32_dev"),
+                                                  ("D2Q37", (512, 12, 1), "fp32_dev"),
                                                   ("D2Q16-GH", (300, 70, 1), "fp32_dev"),
-                                                  ("D3Q39", (300, 6, 9), "bf16_dev")])
+                                                  ("D3Q39", (300, 6, 9), "bf16_dev"),
+                                                  ("D3Q39", (256, 5, 6), "fp32")])
 def test_deterministic_and_tile_independent(lattice, grid, storage):
     lbm = need_gpu()
     outs = []
