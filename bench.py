@@ -83,7 +83,7 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
         mlups = s.ncell / (ms * 1e-3) / 1e6
         gbs = s.bytes_per_step / (ms * 1e-3) / 1e9
         return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, frac=gbs / HBM_PEAK_GBS, tile=tile,
-                    shape=counters.shape_key(info["block"], info["blocks"], info["nontemporal"]),
+                    shape=counters.shape_key(info["block"], info["blocks"], info["nontemporal"], info["vector"]),
                     bytes_per_step=s.bytes_per_step, ncell=s.ncell)
 
 

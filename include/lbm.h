@@ -215,11 +215,12 @@ int32_t lbm_tile_count(const lbm_sim *s);
 lbm_status lbm_set_tile(lbm_sim *s, int32_t tile);
 /* Launch shape of tile `tile` (0 <= tile < lbm_tile_count): threads per workgroup, cells each
  * thread updates (consecutive chunks of a row for the shift kernel, rows of a strip for the
- * Beam-Warming kernel), workgroups per step launch, and whether the step kernel writes with
- * non-temporal stores.  Host only; any output pointer may be NULL.  LBM_EINVAL for a NULL sim
- * or a tile out of range. */
+ * Beam-Warming kernel), cells per vector access (4 for the shift tiles that load and store 4
+ * consecutive cells at once, else 1), workgroups per step launch, and whether the step kernel
+ * writes with non-temporal stores.  Host only; any output pointer may be NULL.  LBM_EINVAL for a
+ * NULL sim or a tile out of range. */
 lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads, int32_t *cells_per_thread,
-                         int64_t *blocks, int32_t *nontemporal);
+                         int32_t *vector_width, int64_t *blocks, int32_t *nontemporal);
 lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile, double *best_ms);
 
 /* Information: cells, populations and bytes moved per step (2 Q ncell * bytes per value). */

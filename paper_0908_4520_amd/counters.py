@@ -41,8 +41,8 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def shape_key(block: int, blocks: int, nontemporal: bool) -> str:
-    return f"{block}x{blocks}" + (":nt" if nontemporal else "")
+def shape_key(block: int, blocks: int, nontemporal: bool, vector: int = 1) -> str:
+    return f"{block}x{blocks}" + (":nt" if nontemporal else "") + (f":v{vector}" if vector > 1 else "")
 
 
 def _template_args(name: str):
@@ -51,9 +51,16 @@ def _template_args(name: str):
 
 
 def _nontemporal(name: str) -> bool:
-    """k_shift_rows<L, N, S, SR, BLOCK, NTS, F>: the sixth template argument."""
+    """k_shift_rows<L, N, S, SR, BLOCK, NTS, F>: the sixth template argument; the vector row
+    kernel k_shift_rows4 always stores non-temporally."""
+    if "k_shift_rows4<" in name:
+        return True
     args = _template_args(name)
     return "k_shift_rows<" in name and len(args) >= 6 and args[5] == "true"
+
+
+def _vector(name: str) -> int:
+    return 4 if "k_shift_rows4<" in name else 1
 
 
 def read_trace(d: str):
@@ -137,12 +144,12 @@ def cmd_traffic(args):
             continue
         print(f"| `{_short(name)}` | {wg} | {nb} | {len(fetch[key])} | {f:.0f} | {w:.0f} | {rd:.4g} | {wr:.4g} |")
         if pat and pat.search(name):
-            ent = {"kernel": name, "block": wg, "blocks": nb, "nontemporal": _nontemporal(name),
+            ent = {"kernel": name, "block": wg, "blocks": nb, "nontemporal": _nontemporal(name), "vector": _vector(name),
                    "fetch_bytes": round(rd), "write_bytes": round(wr), "bytes_per_launch": round(rd + wr),
                    "dispatches": len(fetch[key])}
             if args.alg_read_bytes:
                 ent["fetch_over_algorithmic_read"] = round(rd / args.alg_read_bytes, 4)
-            shapes[shape_key(wg, nb, ent["nontemporal"])] = ent
+            shapes[shape_key(wg, nb, ent["nontemporal"], ent["vector"])] = ent
     if args.json:
         if not shapes:
             raise SystemExit(f"no kernel matches {args.kernel!r}")

@@ -78,8 +78,16 @@ __device__ __forceinline__ double dpp_shl(double old, double v) {
 // with NTS, non-temporal: the output is not read again in this step, and streaming it past
 // the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
 // With F the collision adds the body force of the row and the stress sums are stored.
+// Occupancy hint (waves per SIMD) for the row kernel: the unforced FP16 path with stochastic
+// rounding otherwise settles at 95 registers (5 waves); it fits 80 (6 waves) without spilling.
+template <int S, bool SR, bool F>
+constexpr int row_waves_per_eu() {
+    return (S == ST_FP16_DEV && SR && !F) ? 6 : 1;
+}
+
 template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
-__global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu<S, SR, F>())))
+void k_shift_rows(StepArgs a) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;

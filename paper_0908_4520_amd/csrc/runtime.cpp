@@ -752,13 +752,15 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t tile) {
 }
 
 lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads, int32_t *cells_per_thread,
-                         int64_t *blocks, int32_t *nontemporal) {
+                         int32_t *vector_width, int64_t *blocks, int32_t *nontemporal) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (tile < 0 || tile >= tile_count(s)) return fail(LBM_EINVAL, "tile %d out of range [0, %d)", tile, tile_count(s));
     const StepArgs a = step_args(s, s->buf[0], s->buf[1], tile);
     const bool rows = s->move != LBM_MOVE_BW2 && s->rows_ok;
     if (block_threads) *block_threads = rows ? kShiftTiles[tile].block : kBlock;
-    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile * (rows && kShiftTiles[tile].variant == 3 ? 4 : 1);
+    const int32_t vw = rows && kShiftTiles[tile].variant == 3 ? 4 : 1;
+    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile * vw;
+    if (vector_width) *vector_width = vw;
     if (blocks) *blocks = (int64_t)a.nblocks;
     if (nontemporal) *nontemporal = rows && kShiftTiles[tile].variant != 0;
     return LBM_OK;

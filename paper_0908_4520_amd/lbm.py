@@ -81,8 +81,8 @@ SIGNATURES = {
     "lbm_tile_count": (ctypes.c_int32, [_SIM]),
     "lbm_set_tile": (ctypes.c_int, [_SIM, ctypes.c_int32]),
     "lbm_tile_info": (ctypes.c_int, [_SIM, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
-                                     ctypes.POINTER(ctypes.c_int32)]),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_autotune": (ctypes.c_int, [_SIM, ctypes.c_int32, _I32, _D]),
     "lbm_sizes": (ctypes.c_int, [_SIM, _I64, _I32, _I32, _I64]),
     "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int32,
@@ -304,11 +304,13 @@ class Sim:
         _check(_lib.lbm_set_tile(self._h, t))
 
     def tile_info(self, t: int) -> dict:
-        """Launch shape of tile t: threads per workgroup, cells per thread, workgroups,
-        non-temporal stores."""
-        b, c, n, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
-        _check(_lib.lbm_tile_info(self._h, t, ctypes.byref(b), ctypes.byref(c), ctypes.byref(n), ctypes.byref(nt)))
-        return {"block": b.value, "cells_per_thread": c.value, "blocks": n.value, "nontemporal": bool(nt.value)}
+        """Launch shape of tile t: threads per workgroup, cells per thread, cells per vector
+        access, workgroups, non-temporal stores."""
+        b, c, v, n, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib.lbm_tile_info(self._h, t, ctypes.byref(b), ctypes.byref(c), ctypes.byref(v), ctypes.byref(n),
+                                  ctypes.byref(nt)))
+        return {"block": b.value, "cells_per_thread": c.value, "vector": v.value, "blocks": n.value,
+                "nontemporal": bool(nt.value)}
 
     def autotune(self, steps_per_trial: int = 5):
         t, ms = ctypes.c_int32(), ctypes.c_double()

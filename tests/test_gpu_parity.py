@@ -41,7 +41,7 @@ def test_library_loads_and_reports_sizes():
         assert s.bytes_per_step == 2 * 37 * 300 * 17 * 4
         assert s.tile_count() == 9
         shapes = [s.tile_info(t) for t in range(9)]
-        assert shapes[0] == {"block": 256, "cells_per_thread": 1, "blocks": 2 * 17, "nontemporal": False}
+        assert shapes[0] == {"block": 256, "cells_per_thread": 1, "vector": 1, "blocks": 2 * 17, "nontemporal": False}
         assert {(i["block"], i["nontemporal"]) for i in shapes} == {(256, False), (256, True), (512, True)}
         for i in shapes:   # every row is covered by whole workgroups, with no workgroup to spare
             per_row, cover = i["blocks"] // 17, i["block"] * i["cells_per_thread"]
@@ -248,6 +248,7 @@ def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage):
     p = perm(lattice)
     with lbm.Sim(lattice, N, tau, grid, storage=storage) as s:
         assert s.tile_count() == 11
+        assert [s.tile_info(t)["vector"] for t in range(11)] == [1] * 9 + [4, 4]
         ref = None
         for t in range(s.tile_count()):
             s.set_tile(t)
