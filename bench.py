@@ -106,10 +106,34 @@ def run_batch(lbm, torch, stream, steps=5000, record_every=50):
         end.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(end)
-        return dict(ms_per_step=ms / steps, mlups=b.cells * steps / (ms * 1e-3) / 1e6,
-                    gbs=b.bytes_per_step * steps / (ms * 1e-3) / 1e9, cells=b.cells, steps=steps,
-                    form=form, block=block, bytes_per_step=b.bytes_per_step,
-                    note="effective GB/s: the 115 MB state is resident in the 256 MB Infinity Cache")
+        res = dict(ms_per_step=ms / steps, mlups=b.cells * steps / (ms * 1e-3) / 1e6,
+                   gbs=b.bytes_per_step * steps / (ms * 1e-3) / 1e9, cells=b.cells, steps=steps,
+                   form=form, block=block, bytes_per_step=b.bytes_per_step,
+                   note="effective GB/s: the 115 MB state is resident in the 256 MB Infinity Cache")
+    # the same instances as separate simulations, one step launch per instance and step
+    sims = [lbm.Sim(lat, N, tau, (nx, ny, 1), storage="fp32_dev", stream=stream.cuda_stream)
+            for lat, N, tau, (nx, ny), _ in inst]
+    try:
+        for s in sims:
+            s.set_shear_wave(1e-3, 1)
+        plain_steps = 20
+        for s in sims:
+            s.step(1)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(plain_steps):
+            for s in sims:
+                s.step(1)
+        end.record(stream)
+        torch.cuda.synchronize()
+        pms = start.elapsed_time(end) / plain_steps
+    finally:
+        for s in sims:
+            s.close()
+    res["unbatched_ms_per_step"] = pms
+    res["unbatched_mlups"] = res["cells"] / (pms * 1e-3) / 1e6
+    res["speedup_over_unbatched"] = pms / res["ms_per_step"]
+    return res
 
 
 def run_rdvm(lbm, torch, stream, steps=4000):
@@ -248,7 +272,8 @@ def main():
         r = run_batch(lbm, torch, stream)
         variants["batch_256_instances_5000_steps_fp32_dev"] = {k: (round(v, 4) if isinstance(v, float) else v)
                                                                for k, v in r.items()}
-        log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS (form {r['form']}, block {r['block']})")
+        log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS (form {r['form']}, block {r['block']}); "
+            f"unbatched {r['unbatched_ms_per_step']:.4f} ms/step ({r['speedup_over_unbatched']:.1f}x slower)")
         log("timing the 256-instance reduced-DVM sweep (4000 steps) ...")
         r = run_rdvm(lbm, torch, stream)
         if not args.no_cpu_baseline:

@@ -155,8 +155,8 @@ int64_t lbm_step_count(const lbm_sim *s);
  * and lbm_totals report the physical velocity rho u = sum_a xi_a f*_a - rho G/2 (G the force
  * times dt of the latest collision, none at step 0).  amplitude 0 keeps the forced kernels
  * (and the stress below); wave_axis 0 switches back to the unforced kernels.  The row-tiled
- * forced kernel has 4 tiles (the 256-thread plain-store ones).  Allocates two small device
- * tables.  LBM_EINVAL for an invalid axis or non-finite values. */
+ * forced kernel has 7 tiles (the 256-thread plain-store and the 512-thread non-temporal ones).
+ * Allocates two small device tables.  LBM_EINVAL for an invalid axis or non-finite values. */
 lbm_status lbm_set_force(lbm_sim *s, double amplitude, double frequency, int32_t wave_axis);
 
 /* Sine and cosine projections over the force's wave axis (as lbm_shear_amplitude) of the

@@ -106,8 +106,9 @@ struct KernelSet {
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
     StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
     StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision
-    // The same with the body force (256 threads, plain stores for the row tiles)
-    StepFn shift_rows_forced;
+    // The same with the body force (row tiles: 256 threads with plain stores, 512 threads with
+    // non-temporal stores)
+    StepFn shift_rows_forced[2];
     StepFn shift_cells_forced;
     StepBW32 bw2_f32_forced;
     StepBW64 bw2_f64_forced;

@@ -633,7 +633,8 @@ KernelSet make_set() {
         k.shift_rows[1] = &launch_shift_rows<L, N, S, SR, 256, true, false>;
         k.shift_rows[2] = &launch_shift_rows<L, N, S, SR, 512, true, false>;
         k.shift_cells = &launch_shift_cells<L, N, S, SR, false>;
-        k.shift_rows_forced = &launch_shift_rows<L, N, S, SR, 256, false, true>;
+        k.shift_rows_forced[0] = &launch_shift_rows<L, N, S, SR, 256, false, true>;
+        k.shift_rows_forced[1] = &launch_shift_rows<L, N, S, SR, 512, true, true>;
         if constexpr (max_cx<L>() <= 4 && (S == ST_FP32 || S == ST_FP32_DEV))
             k.shift_rows4 = &launch_shift_rows4<L, N, S, SR, true>;
         k.shift_cells_forced = &launch_shift_cells<L, N, S, SR, true>;

@@ -193,6 +193,13 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     return a;
 }
 
+// Per-wave stress sums a forced step with tile tile_index stores.
+uint32_t stress_slots(const lbm_sim *s, int tile_index) {
+    const uint32_t waves = (s->move != LBM_MOVE_BW2 && s->rows_ok) ? (uint32_t)kShiftTiles[tile_index].block / 64u
+                                                                   : (uint32_t)(kBlock / 64);
+    return step_args(s, s->buf[0], s->buf[1], tile_index).nblocks * waves;
+}
+
 // One step from fin to fout with tile tile_index.  A forced simulation runs the forced
 // kernels; with record_stress they also store the per-wave stress sums.
 hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, bool record_stress) {
@@ -204,7 +211,7 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
         a.force_sin = s->d_ftab + (s->f_axis == 1 ? s->g.ny : s->g.nz);
         a.force_axis = s->f_axis;
         if (record_stress) {
-            const uint32_t slots = a.nblocks * (uint32_t)(kBlock / 64);   // forced kernels: 256 threads
+            const uint32_t slots = stress_slots(s, tile_index);
             if (slots > s->stress_cap) return hipErrorInvalidValue;
             a.stress = s->d_stress;
             s->stress_slots = slots;
@@ -212,7 +219,8 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
         if (s->move == LBM_MOVE_BW2)
             return s->o.storage == LBM_FP64 ? k->bw2_f64_forced(a, s->bwd, s->stream)
                                             : k->bw2_f32_forced(a, s->bwf, s->stream);
-        return s->rows_ok ? k->shift_rows_forced(a, s->stream) : k->shift_cells_forced(a, s->stream);
+        if (!s->rows_ok) return k->shift_cells_forced(a, s->stream);
+        return k->shift_rows_forced[kShiftTiles[tile_index].variant == 2 ? 1 : 0](a, s->stream);
     }
     if (s->move == LBM_MOVE_BW2)
         return s->o.storage == LBM_FP64 ? k->bw2_f64(a, s->bwd, s->stream) : k->bw2_f32(a, s->bwf, s->stream);
@@ -221,8 +229,8 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
     return v == 3 ? k->shift_rows4(a, s->stream) : k->shift_rows[v](a, s->stream);
 }
 
-// The forced row kernel exists in the plain 256-thread form only: the first four shift tiles.
-constexpr int kForcedShiftTiles = 4;
+// The forced row kernel exists as variants 0 and 2 only: the first seven shift tiles.
+constexpr int kForcedShiftTiles = 7;
 
 // The vector tiles need their kernel (FP32 storages, |c_x| <= 4) and whole 256-cell waves.
 bool vector_tiles_ok(const lbm_sim *s) { return s->ks->shift_rows4 != nullptr && s->g.nx % 256 == 0; }
@@ -700,8 +708,7 @@ lbm_status lbm_set_force(lbm_sim *s, double amplitude, double frequency, int32_t
     const bool was = s->forced;
     s->forced = true;
     uint32_t cap = 0;
-    for (int t = 0; t < tile_count(s); ++t)
-        cap = std::max(cap, step_args(s, s->buf[0], s->buf[1], t).nblocks * (uint32_t)(kBlock / 64));
+    for (int t = 0; t < tile_count(s); ++t) cap = std::max(cap, stress_slots(s, t));
     s->forced = was;
     double *tab = nullptr, *stress = nullptr;
     hipError_t e = hipMalloc(&tab, sizeof(double) * h.size());
