@@ -259,15 +259,21 @@ lbm_status lbm_batch_reset(lbm_batch *b);
 lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, double *amp);
 /* Decoded FP64 populations f[a * ncell + cell] of instance `index` (ncell = nx * ny). */
 lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f);
-/* Two persistent forms: form 0 gives each instance one workgroup for the whole run (no
+/* Three persistent forms: form 0 gives each instance one workgroup for the whole run (no
  * synchronisation across CUs; the largest instance bounds the run time); form 1 cuts every
  * instance into chunks of one cell per thread, spreads them over a grid that is resident at
  * once, and meets at a device-wide barrier after every step (if the barrier's bounded wait
- * expires, the run stops and returns LBM_EDEVICE).  Workgroup size 256, 512 or 1024.
- * lbm_batch_set_form picks one; lbm_batch_autotune times every (form, size) pair over
- * `steps` steps, keeps the fastest and restores the state as it was. */
+ * expires, the run stops and returns LBM_EDEVICE); form 2 is form 1 with all chunks of an
+ * instance on workgroups of one XCD and a barrier per XCD (no data crosses an XCD's L2).
+ * Form 2 needs the grid's workgroups spread evenly over the XCDs: lbm_batch_set_form returns
+ * LBM_EDEVICE if a probe launch finds otherwise, and if a run finds otherwise it changes
+ * nothing, switches the batch to form 1 and runs in that form.  Workgroup size 256, 512 or
+ * 1024.  lbm_batch_set_form picks one; lbm_batch_autotune times every (form, size) pair over
+ * `steps` steps, keeps the fastest and restores the state as it was; lbm_batch_form reports
+ * the form and size in use. */
 lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block);
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_t *block, double *ms_per_step);
+lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block);
 /* Total cells and algorithmic bytes per step (2 Q ncell x bytes per value, summed). */
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
 void lbm_batch_free(lbm_batch *b);   /* NULL-safe */

@@ -42,13 +42,23 @@ struct BatchArgs {
     uint32_t nwg;               // workgroups of the grid form
     uint32_t nrec;              // amplitudes per instance in this run
     uint32_t *barrier;          // device-wide barrier counter (zeroed before the launch)
-    int32_t *abort;             // set if a barrier wait exceeded its bound
+    int32_t *abort;             // 1: a barrier wait exceeded its bound; 2: XCD placement differs from the plan
     double *partials;           // per chunk and record: FP64 sums
+    // XCD-local grid form: workgroup slot s on XCD x runs the chunks of plan entry x * wg_per_xcd + s
+    uint32_t *sync;             // per-XCD counters, see kSyncWords (zeroed before the launch)
+    uint32_t nxcd, wg_per_xcd;
 };
 
-// form 0: one workgroup per instance; form 1: chunks over a resident grid with a barrier per step.
+// Per-XCD counters of the XCD-local form, one 128-byte line each: sync[x * kSyncStride] counts
+// the slots taken on XCD x, sync[(kMaxXcd + x) * kSyncStride] its barrier arrivals.
+constexpr uint32_t kMaxXcd = 16, kSyncStride = 32, kSyncWords = 2 * kMaxXcd * kSyncStride;
+
+// form 0: one workgroup per instance; form 1: chunks over a resident grid with a device-wide
+// barrier per step; form 2: the same with every instance's chunks on one XCD and a barrier per XCD.
 hipError_t launch_batch(int storage, int form, int block, const BatchArgs &a, uint32_t count, hipStream_t s);
-int batch_grid_resident_per_cu(int storage, int block);
+int batch_grid_resident_per_cu(int storage, int form, int block);
+// XCD (accelerator complex die) of every one of n workgroups of a small probe launch: out[b].
+hipError_t probe_xcd(uint32_t *out, uint32_t n, hipStream_t s);
 bool batch_supports(int lattice, int order, int storage);
 
 }  // namespace lbm

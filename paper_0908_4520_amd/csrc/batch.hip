@@ -1,6 +1,6 @@
 // batch.hip -- many independent shear-wave instances advanced in one persistent launch.
 //
-// Two persistent forms, chosen by timing (lbm_batch_autotune):
+// Three persistent forms, chosen by timing (lbm_batch_autotune):
 //  * per-instance: each workgroup owns one whole instance for the run and loops over the
 //    steps with a workgroup barrier between them; nothing synchronises across CUs, but the
 //    run lasts as long as the largest instance takes on one CU;
@@ -10,6 +10,16 @@
 //    step.  The barrier spins on an agent-scope counter with a bounded number of sleeps; if
 //    the bound is hit (workgroups not resident together) it raises an abort flag that every
 //    workgroup checks, so all of them leave the loop and the host reports the failure.
+//    Each XCD has its own L2 and the L2s are not coherent with each other, so every arrival
+//    writes back and every departure invalidates the workgroup's whole L2: on a full grid that
+//    is hundreds of L2 flushes per step, which stall the loads of every workgroup still working;
+//  * XCD-local grid: the same chunks, but all chunks of an instance go to workgroups of one
+//    XCD, so no data crosses an L2 and a step ends at a barrier of that XCD's workgroups only.
+//    Stores are visible to the XCD once they reach its L2, so the barrier needs only a wait
+//    for the stores and an L1 invalidate, no L2 writeback.  A workgroup reads which XCD it runs
+//    on and takes the next slot there; one device-wide barrier at the start checks that every
+//    XCD received the planned number of workgroups, and if not, every workgroup leaves before
+//    touching the state and the host falls back to the device-wide form.
 // Amplitudes: the sine projection of u_x is summed in FP64 per chunk (fixed order) and the
 // per-instance sums are formed by a second kernel in a fixed order, so runs are bitwise
 // reproducible.
@@ -217,11 +227,76 @@ __device__ bool grid_barrier(const BatchArgs &a, uint32_t gen, int *flag) {
     return *flag == 0;
 }
 
-template <int S, int BLOCK>
+// XCD the calling wave runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ uint32_t xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
+
+// Barrier number `gen` (1, 2, ...) of the workgroups on XCD x.  They share that XCD's L2: each
+// wave waits until its stores have reached the L2, thread 0 counts the workgroup in and waits
+// for the others, and then every wave invalidates its CU's L1 (buffer_inv at group scope, the
+// invalidate the compiler itself issues for a workgroup acquire when a workgroup may span CUs)
+// so that its later loads are served from the L2.  An agent-scope acquire would do as well but
+// also invalidates the XCD's L2, which the other workgroups are still reading from.  Returns
+// false if the run was aborted.
+__device__ bool xcd_barrier(const BatchArgs &a, uint32_t x, uint32_t gen, int *flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);   // vmcnt(0): this wave's stores are acknowledged by the L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *ctr = a.sync + (kMaxXcd + x) * kSyncStride;
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = gen * a.wg_per_xcd;
+        uint32_t spins = 0;
+        int ab = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins >= 2 * kSpinLimit) {
+                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+        }
+        *flag = ab;
+    }
+    __syncthreads();
+    asm volatile("buffer_inv sc0" ::: "memory");
+    return *flag == 0;
+}
+
+// XCD: false for the device-wide form (plan entry = blockIdx.x), true for the XCD-local form.
+template <int S, int BLOCK, bool XCD>
 __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
     __shared__ double red[BLOCK / 64];
     __shared__ int flag;
-    const uint32_t c0 = a.wg_first[blockIdx.x], c1 = a.wg_first[blockIdx.x + 1];
+    __shared__ uint32_t place[2];   // XCD, plan entry
+    if constexpr (XCD) {
+        if (threadIdx.x == 0) {
+            const uint32_t x = xcd_id();
+            uint32_t p = ~0u;
+            if (x < a.nxcd) {
+                const uint32_t slot = __hip_atomic_fetch_add(a.sync + x * kSyncStride, 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                if (slot < a.wg_per_xcd) p = x * a.wg_per_xcd + slot;
+            }
+            if (p == ~0u) __hip_atomic_store(a.abort, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            place[0] = x;
+            place[1] = p;
+        }
+        // every workgroup has its slot; a placement that differs from the plan is seen by all
+        if (!grid_barrier(a, 1, &flag)) return;
+        if (threadIdx.x == 0) flag = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (flag) return;
+    } else {
+        if (threadIdx.x == 0) {
+            place[0] = 0;
+            place[1] = blockIdx.x;
+        }
+        __syncthreads();
+    }
+    const uint32_t xcd = place[0], entry = place[1];
+    const uint32_t c0 = a.wg_first[entry], c1 = a.wg_first[entry + 1];
     auto record = [&](int k, int64_t done) {
         for (uint32_t c = c0; c < c1; ++c) {
             const BatchChunk ch = a.chunks[a.wg_chunks[c]];
@@ -239,7 +314,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
             const BatchInst in = a.inst[ch.inst];
             step_chunk<S>(in, a, a.cur[ch.inst] ^ (int)(step & 1), ch.start, ch.count);
         }
-        if (!grid_barrier(a, ++gen, &flag)) return;
+        if constexpr (XCD) {
+            if (!xcd_barrier(a, xcd, ++gen, &flag)) return;
+        } else {
+            if (!grid_barrier(a, ++gen, &flag)) return;
+        }
         if (a.record > 0 && (step + 1) % a.record == 0) record((int)((step + 1) / a.record), step + 1);
     }
 }
@@ -254,11 +333,22 @@ __global__ __launch_bounds__(256) void k_batch_amp(BatchArgs a, uint32_t count) 
     a.amp[a.inst[i].amp_off + k] = 2.0 * s / (double)a.inst[i].ncell;
 }
 
-__global__ void k_batch_reset(BatchArgs a) {
+__global__ __launch_bounds__(256) void k_batch_reset(BatchArgs a) {
     if (threadIdx.x == 0) {
         *a.barrier = 0u;
         *a.abort = 0;
     }
+    if (a.sync)
+        for (uint32_t i = threadIdx.x; i < kSyncWords; i += 256) a.sync[i] = 0u;
+}
+
+__global__ __launch_bounds__(64) void k_probe_xcd(uint32_t *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcd_id();
+}
+
+hipError_t probe_xcd(uint32_t *out, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_xcd, dim3(n), dim3(64), 0, s, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- host launchers
@@ -268,10 +358,13 @@ hipError_t launch_t(int form, const BatchArgs &a, uint32_t count, hipStream_t s)
         hipLaunchKernelGGL((k_batch<S, BLOCK>), dim3(count), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_grid<S, BLOCK>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+    if (form == 2)
+        hipLaunchKernelGGL((k_batch_grid<S, BLOCK, true>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_batch_grid<S, BLOCK, false>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess || (a.record <= 0 && !a.record_first)) return e;
     const uint64_t n = (uint64_t)count * a.nrec;
@@ -293,19 +386,21 @@ hipError_t launch_batch(int storage, int form, int block, const BatchArgs &a, ui
     return hipErrorInvalidValue;
 }
 
-template <int S, int BLOCK>
+template <int S, int BLOCK, bool XCD>
 int resident_t() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_grid<S, BLOCK>, BLOCK, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_grid<S, BLOCK, XCD>, BLOCK, 0) != hipSuccess) return 0;
     return n;
 }
 
-int batch_grid_resident_per_cu(int storage, int block) {
-    if (storage == ST_FP32_DEV)
-        return block == 256 ? resident_t<ST_FP32_DEV, 256>() : block == 512 ? resident_t<ST_FP32_DEV, 512>()
-                                                                            : resident_t<ST_FP32_DEV, 1024>();
-    return block == 256 ? resident_t<ST_FP64, 256>() : block == 512 ? resident_t<ST_FP64, 512>()
-                                                                     : resident_t<ST_FP64, 1024>();
+template <int S, bool XCD>
+int resident_b(int block) {
+    return block == 256 ? resident_t<S, 256, XCD>() : block == 512 ? resident_t<S, 512, XCD>() : resident_t<S, 1024, XCD>();
+}
+
+int batch_grid_resident_per_cu(int storage, int form, int block) {
+    if (storage == ST_FP32_DEV) return form == 2 ? resident_b<ST_FP32_DEV, true>(block) : resident_b<ST_FP32_DEV, false>(block);
+    return form == 2 ? resident_b<ST_FP64, true>(block) : resident_b<ST_FP64, false>(block);
 }
 
 bool batch_supports(int lattice, int order, int storage) {

@@ -839,12 +839,16 @@ struct lbm_batch {
     double *d_bw = nullptr;
     double *d_amp = nullptr;
     size_t amp_cap = 0;                     // doubles allocated in d_amp
-    int form = 0;                           // 0: workgroup per instance, 1: chunks + grid barrier
+    int form = 0;                           // 0: workgroup per instance, 1: chunks + grid barrier,
+                                            // 2: chunks + barrier per XCD
     int block = 512;
     int64_t cells = 0, bytes_per_step = 0;
-    // grid-form plan (for plan_block)
-    int plan_block = 0;
+    // grid-form plan (for plan_block, plan_form)
+    int plan_block = 0, plan_form = 0;
     uint32_t nchunks = 0, nwg = 0;
+    int nxcd = 0;                           // XCDs seen by the probe (0: not probed, -1: form 2 unusable)
+    uint32_t wg_per_xcd = 0;
+    uint32_t *d_sync = nullptr;
     BatchChunk *d_chunks = nullptr;
     uint32_t *d_inst_first = nullptr, *d_wg_first = nullptr, *d_wg_chunks = nullptr;
     uint32_t *d_barrier = nullptr;
@@ -897,15 +901,60 @@ lbm_status realloc_dev(P **p, size_t bytes) {
     return LBM_OK;
 }
 
-// Chunks of `block` cells per instance; chunks spread over the resident grid, each chunk
-// (largest cost first) onto the least-loaded workgroup.
-lbm_status batch_plan(lbm_batch *b, int block) {
-    if (b->plan_block == block) return LBM_OK;
+// Longest-processing-time-first: items (largest cost first) onto the least-loaded of n bins.
+std::vector<std::vector<uint32_t>> lpt(const std::vector<uint32_t> &items, const std::vector<double> &cost, uint32_t n) {
+    std::vector<uint32_t> idx(items);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+    std::vector<double> load(n, 0.0);
+    std::vector<std::vector<uint32_t>> lists(n);
+    for (uint32_t k : idx) {
+        uint32_t best = 0;
+        for (uint32_t w = 1; w < n; ++w)
+            if (load[w] < load[best]) best = w;
+        load[best] += cost[k];
+        lists[best].push_back(k);
+    }
+    for (auto &l : lists) std::sort(l.begin(), l.end());
+    return lists;
+}
+
+// Number of XCDs, from the XCD ids of a probe launch of n workgroups (the grid size of the
+// XCD-local form); -1 if the workgroups were not spread evenly over them.
+lbm_status batch_probe_xcd(lbm_batch *b, uint32_t n) {
+    uint32_t *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(uint32_t) * n));
+    std::vector<uint32_t> h(n);
+    hipError_t e = probe_xcd(d, n, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(d);
+    HIP_TRY(e);
+    uint32_t nx = 0;
+    for (uint32_t v : h) nx = std::max(nx, v + 1);
+    std::vector<uint32_t> per(nx, 0);
+    for (uint32_t v : h) ++per[v];
+    bool even = nx >= 1 && nx <= kMaxXcd;
+    for (uint32_t c : per) even = even && c == per[0];
+    b->nxcd = even ? (int)nx : -1;
+    return LBM_OK;
+}
+
+// Chunks of `block` cells per instance.  Form 1: chunks spread over the resident grid, each
+// chunk (largest cost first) onto the least-loaded workgroup.  Form 2: instances (largest
+// first) onto the least-loaded XCD, then each XCD's chunks over its share of the grid.
+lbm_status batch_plan(lbm_batch *b, int block, int form) {
+    if (b->plan_block == block && b->plan_form == form) return LBM_OK;
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = batch_grid_resident_per_cu((int)b->storage, block);
+    const int per_cu = batch_grid_resident_per_cu((int)b->storage, form, block);
     if (per_cu < 1 || ncu < 1) return fail(LBM_EDEVICE, "grid form cannot be resident with %d threads", block);
+    const uint32_t resident = (uint32_t)(per_cu * ncu);
+    lbm_status st;
+    if (form == 2) {
+        if (b->nxcd == 0 && (st = batch_probe_xcd(b, resident)) != LBM_OK) return st;
+        if (b->nxcd < 1) return fail(LBM_EDEVICE, "workgroups are not spread evenly over XCDs: XCD-local form unusable");
+    }
     std::vector<BatchChunk> chunks;
     std::vector<uint32_t> inst_first(b->count + 1, 0);
     std::vector<double> cost;
@@ -913,7 +962,10 @@ lbm_status batch_plan(lbm_batch *b, int block) {
         inst_first[i] = (uint32_t)chunks.size();
         const BatchInst &d = b->desc[i];
         const LatInfo *L = lat_info(d.lattice);
-        const double per_cell = (double)L->Q * (L->on_lattice ? 1.0 : 2.5);
+        // time per cell of one step, fitted to per-instance runs of one 512-thread workgroup per
+        // CU on MI355X (ns): D2Q9 4.0, D2Q37 8.8 (exact shift), D2Q16-GH 11.5, D2Q36-GH 25
+        // (Beam-Warming reads three rows per population and applies two difference stencils)
+        const double per_cell = L->on_lattice ? 2.5 + 0.17 * L->Q : 0.7 + 0.68 * L->Q;
         for (uint32_t s0 = 0; s0 < d.ncell; s0 += (uint32_t)block) {
             const uint32_t n = std::min<uint32_t>((uint32_t)block, d.ncell - s0);
             chunks.push_back(BatchChunk{i, s0, n});
@@ -922,27 +974,42 @@ lbm_status batch_plan(lbm_batch *b, int block) {
     }
     inst_first[b->count] = (uint32_t)chunks.size();
     const uint32_t nchunks = (uint32_t)chunks.size();
-    const uint32_t nwg = std::min<uint32_t>(nchunks, (uint32_t)(per_cu * ncu));
-    std::vector<uint32_t> idx(nchunks);
-    for (uint32_t k = 0; k < nchunks; ++k) idx[k] = k;
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
-    std::vector<double> load(nwg, 0.0);
-    std::vector<std::vector<uint32_t>> lists(nwg);
-    for (uint32_t k : idx) {
-        uint32_t best = 0;
-        for (uint32_t w = 1; w < nwg; ++w)
-            if (load[w] < load[best]) best = w;
-        load[best] += cost[k];
-        lists[best].push_back(k);
+    std::vector<std::vector<uint32_t>> lists;
+    uint32_t nwg = 0, per_xcd = 0;
+    if (form == 2) {
+        const uint32_t nx = (uint32_t)b->nxcd;
+        std::vector<uint32_t> insts(b->count);
+        std::vector<double> icost(b->count, 0.0);
+        for (int i = 0; i < b->count; ++i) {
+            insts[i] = (uint32_t)i;
+            for (uint32_t c = inst_first[i]; c < inst_first[i + 1]; ++c) icost[i] += cost[c];
+        }
+        const auto bins = lpt(insts, icost, nx);
+        size_t most = 1;
+        std::vector<std::vector<uint32_t>> xchunks(nx);
+        for (uint32_t x = 0; x < nx; ++x) {
+            for (uint32_t i : bins[x])
+                for (uint32_t c = inst_first[i]; c < inst_first[i + 1]; ++c) xchunks[x].push_back(c);
+            most = std::max(most, xchunks[x].size());
+        }
+        per_xcd = (uint32_t)std::min<size_t>(most, std::max<uint32_t>(1u, resident / nx));
+        nwg = per_xcd * nx;
+        for (uint32_t x = 0; x < nx; ++x) {
+            auto part = lpt(xchunks[x], cost, per_xcd);
+            for (auto &l : part) lists.push_back(std::move(l));
+        }
+    } else {
+        nwg = std::min<uint32_t>(nchunks, resident);
+        std::vector<uint32_t> all(nchunks);
+        for (uint32_t k = 0; k < nchunks; ++k) all[k] = k;
+        lists = lpt(all, cost, nwg);
     }
     std::vector<uint32_t> wg_first(nwg + 1, 0), wg_chunks;
     for (uint32_t w = 0; w < nwg; ++w) {
-        std::sort(lists[w].begin(), lists[w].end());
         wg_first[w] = (uint32_t)wg_chunks.size();
         wg_chunks.insert(wg_chunks.end(), lists[w].begin(), lists[w].end());
     }
     wg_first[nwg] = (uint32_t)wg_chunks.size();
-    lbm_status st;
     if ((st = realloc_dev(&b->d_chunks, sizeof(BatchChunk) * nchunks)) != LBM_OK) return st;
     if ((st = realloc_dev(&b->d_inst_first, sizeof(uint32_t) * inst_first.size())) != LBM_OK) return st;
     if ((st = realloc_dev(&b->d_wg_first, sizeof(uint32_t) * wg_first.size())) != LBM_OK) return st;
@@ -954,7 +1021,9 @@ lbm_status batch_plan(lbm_batch *b, int block) {
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->nchunks = nchunks;
     b->nwg = nwg;
+    b->wg_per_xcd = per_xcd;
     b->plan_block = block;
+    b->plan_form = form;
     b->partials_cap = 0;
     batch_drop_graph(b);
     return LBM_OK;
@@ -968,7 +1037,7 @@ lbm_status batch_ensure_logs(lbm_batch *b, size_t per) {
         b->amp_cap = n_amp;
         batch_drop_graph(b);
     }
-    if (b->form == 1) {
+    if (b->form >= 1) {
         const size_t n_part = per * (size_t)b->nchunks;
         if (n_part > b->partials_cap) {
             lbm_status st = realloc_dev(&b->d_partials, sizeof(double) * n_part);
@@ -1001,15 +1070,19 @@ BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t 
     a.barrier = b->d_barrier;
     a.abort = b->d_abort;
     a.partials = b->d_partials;
+    a.sync = b->form == 2 ? b->d_sync : nullptr;
+    a.nxcd = b->nxcd > 0 ? (uint32_t)b->nxcd : 0u;
+    a.wg_per_xcd = b->wg_per_xcd;
     return a;
 }
 
-lbm_status batch_check_abort(lbm_batch *b) {
-    if (b->form != 1) return LBM_OK;
-    int32_t ab = 0;
-    HIP_TRY(hipMemcpyAsync(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+// The abort flag of the last grid-form launch: 0 ok, 1 a barrier wait expired, 2 the XCD
+// placement differed from the plan (nothing was stepped).
+lbm_status batch_abort_flag(lbm_batch *b, int32_t *ab) {
+    *ab = 0;
+    if (b->form == 0) return LBM_OK;
+    HIP_TRY(hipMemcpyAsync(ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    if (ab) return fail(LBM_EDEVICE, "batch grid barrier timed out: workgroups were not resident together");
     return LBM_OK;
 }
 
@@ -1104,6 +1177,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     if (e == hipSuccess) e = hipMalloc(&b->d_bw, sizeof(double) * bw_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_barrier, sizeof(uint32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int32_t) * 2);
+    if (e == hipSuccess) e = hipMalloc(&b->d_sync, sizeof(uint32_t) * kSyncWords);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_sin, sin_h.data(), sizeof(double) * sin_h.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_bw, bw_h.data(), sizeof(double) * bw_h.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, b->stream);
@@ -1131,7 +1205,7 @@ void lbm_batch_free(lbm_batch *b) {
     for (void *p : {b->pool, (void *)b->d_inst, (void *)b->d_order, (void *)b->d_cur, (void *)b->d_sin,
                     (void *)b->d_bw, (void *)b->d_amp, (void *)b->d_chunks, (void *)b->d_inst_first,
                     (void *)b->d_wg_first, (void *)b->d_wg_chunks, (void *)b->d_barrier, (void *)b->d_abort,
-                    (void *)b->d_partials})
+                    (void *)b->d_partials, (void *)b->d_sync})
         if (p) (void)hipFree(p);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -1156,7 +1230,7 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
     if (per * (int64_t)b->count > (1ll << 31)) return fail(LBM_EINVAL, "amplitude log too large");
     const int32_t rec = amp ? record_every : 0, first = amp ? 1 : 0;
     lbm_status st;
-    if (b->form == 1 && (st = batch_plan(b, b->block)) != LBM_OK) return st;
+    if (b->form >= 1 && (st = batch_plan(b, b->block, b->form)) != LBM_OK) return st;
     if ((st = batch_ensure_logs(b, (size_t)per)) != LBM_OK) return st;
     bool changed = false;
     for (int i = 0; i < b->count; ++i) {
@@ -1189,7 +1263,16 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
     HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
     if (amp) HIP_TRY(hipMemcpyAsync(amp, b->d_amp, sizeof(double) * per * b->count, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    if ((st = batch_check_abort(b)) != LBM_OK) return st;
+    int32_t ab = 0;
+    if ((st = batch_abort_flag(b, &ab)) != LBM_OK) return st;
+    if (ab == 2) {
+        // the workgroups did not land on the XCDs as planned and left before stepping:
+        // run again in the device-wide form and keep it
+        b->nxcd = -1;
+        if ((st = lbm_batch_set_form(b, 1, b->block)) != LBM_OK) return st;
+        return lbm_batch_run(b, steps, record_every, amp);
+    }
+    if (ab) return fail(LBM_EDEVICE, "batch grid barrier timed out: workgroups were not resident together");
     if (steps & 1)
         for (auto &c : b->cur) c ^= 1;
     return LBM_OK;
@@ -1230,12 +1313,19 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
     int best_form = b->form, best_block = b->block;
     float best_ms = 1e30f;
     lbm_status st = LBM_OK;
-    for (int form : {0, 1}) {
+    for (int form : {0, 1, 2}) {
         for (int blk : {1024, 512, 256}) {
             if (e != hipSuccess || st != LBM_OK) break;
-            if (form == 1) {
-                if (batch_grid_resident_per_cu((int)b->storage, blk) < 1) continue;
-                if ((st = batch_plan(b, blk)) != LBM_OK) break;
+            if (form >= 1) {
+                if (batch_grid_resident_per_cu((int)b->storage, form, blk) < 1) continue;
+                if (form == 2 && b->nxcd < 0) continue;
+                if ((st = batch_plan(b, blk, form)) != LBM_OK) {
+                    if (form == 2 && b->nxcd < 0) {   // XCD-local form unusable here: skip it
+                        st = LBM_OK;
+                        continue;
+                    }
+                    break;
+                }
             }
             const int saved_form = b->form;
             b->form = form;
@@ -1249,8 +1339,9 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
             float ms = 0;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             int32_t ab = 0;
-            if (e == hipSuccess && form == 1) {
+            if (e == hipSuccess && form >= 1) {
                 e = hipMemcpy(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost);
+                if (e == hipSuccess && ab == 2) b->nxcd = -1;
             }
             if (e == hipSuccess && !ab && ms < best_ms) {
                 best_ms = ms;
@@ -1269,19 +1360,26 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
     batch_drop_graph(b);
     b->form = best_form;
     b->block = best_block;
-    if (b->form == 1 && (st = batch_plan(b, b->block)) != LBM_OK) return st;
+    if (b->form >= 1 && (st = batch_plan(b, b->block, b->form)) != LBM_OK) return st;
     if (form) *form = best_form;
     if (block) *block = best_block;
     if (ms_per_step) *ms_per_step = (double)best_ms / steps;
     return LBM_OK;
 }
 
+lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (form) *form = b->form;
+    if (block) *block = b->block;
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
-    if ((form != 0 && form != 1) || (block != 256 && block != 512 && block != 1024))
-        return fail(LBM_EINVAL, "form must be 0 or 1 and block 256, 512 or 1024");
-    if (form == 1) {
-        lbm_status st = batch_plan(b, block);
+    if ((form < 0 || form > 2) || (block != 256 && block != 512 && block != 1024))
+        return fail(LBM_EINVAL, "form must be 0, 1 or 2 and block 256, 512 or 1024");
+    if (form >= 1) {
+        lbm_status st = batch_plan(b, block, form);
         if (st != LBM_OK) return st;
     }
     batch_drop_graph(b);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "lbm_batch_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D]),
     "lbm_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _I32, _I32, _D]),
     "lbm_batch_set_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_batch_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_gauss_hermite": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
@@ -382,6 +383,12 @@ class Batch:
 
     def set_form(self, form: int, block: int):
         _check(_lib.lbm_batch_set_form(self._h, form, block))
+
+    def form(self):
+        """(form, block) in use (a run can move form 2 to form 1)."""
+        f, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lbm_batch_form(self._h, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
 
 
 def lbm_gauss_hermite(n: int):

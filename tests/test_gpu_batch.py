@@ -35,7 +35,7 @@ SMALL = [("D2Q9", 2, 0.3, 4, 40), ("D2Q37", 4, 0.05, 4, 50), ("D2Q16-GH", 3, 1.0
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32_dev"])
-@pytest.mark.parametrize("form,block", [(0, 256), (0, 1024), (1, 256), (1, 512)])
+@pytest.mark.parametrize("form,block", [(0, 256), (0, 1024), (1, 256), (1, 512), (2, 256), (2, 1024)])
 def test_small_mixed_batch_matches_oracle(storage, form, block):
     lbm = need_gpu()
     inst = []
@@ -46,6 +46,7 @@ def test_small_mixed_batch_matches_oracle(storage, form, block):
     with lbm.Batch(inst, storage=storage) as b:
         b.set_form(form, block)
         amp = b.run(steps, every)
+        assert b.form() == (form, block)
         pops = [b.populations(i) for i in range(len(inst))]
     tol_a = 1e-12 if storage == "fp64" else 1e-5
     tol_f = 1e-12 if storage == "fp64" else 1e-5
@@ -57,15 +58,15 @@ def test_small_mixed_batch_matches_oracle(storage, form, block):
         assert da <= tol_a and df <= tol_f
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_batch_graph_replay_equals_one_long_run(form):
     """Two replays of the captured 20-step graph (with host work between) give exactly the
-    populations of one 40-step run, in either persistent form, and the forms agree."""
+    populations of one 40-step run, in every persistent form, and the forms agree."""
     lbm = need_gpu()
     inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, kn, nx, ny in SMALL if not math.isinf(kn)]
     with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
         a.set_form(form, 512)
-        b.set_form(1 - form, 256)
+        b.set_form((form + 1) % 3, 256)
         a.run(20, 5)
         _ = [a.populations(i) for i in range(2)]
         a.run(20, 5)
@@ -82,11 +83,32 @@ def test_batch_autotune_keeps_state():
         a.run(7, 7)
         b.run(7, 7)
         form, blk, ms = a.autotune(5)
-        assert form in (0, 1) and blk in (256, 512, 1024) and ms > 0
+        assert form in (0, 1, 2) and blk in (256, 512, 1024) and ms > 0
         a.run(9, 3)
         b.run(9, 3)
         for i in range(len(inst)):
             assert np.array_equal(a.populations(i), b.populations(i))
+
+
+@pytest.mark.parametrize("block", [256, 1024])
+def test_xcd_local_form_equals_device_wide_form_on_the_sweep(block):
+    """The full Kn sweep (256 instances, seed 0) over 60 steps: the XCD-local form gives every
+    instance bit for bit the populations and amplitudes of the device-wide form (same
+    arithmetic; only where the chunks run and how the steps are synchronised differ), so no
+    load saw a stale cache line."""
+    from paper_0908_4520_amd import workloads
+    lbm = need_gpu()
+    inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, nx, ny, kn in workloads.batch_instances(0, 256)]
+    with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(1, block)
+        b.set_form(2, block)
+        amp_a = a.run(60, 20)
+        amp_b = b.run(60, 20)
+        assert b.form() == (2, block) and a.form() == (1, block)
+        assert np.array_equal(amp_a, amp_b)
+        for i in range(0, 256, 5):
+            assert np.array_equal(a.populations(i), b.populations(i)), i
+    say(f"XCD-local form, block {block}: 256 instances x 60 steps bitwise equal to the device-wide form")
 
 
 def _linear_series(lat, tau, ny, steps, every):
