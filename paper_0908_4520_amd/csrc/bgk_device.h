@@ -125,7 +125,9 @@ struct Codec<ST_BF16_DEV> {
     template <bool SR>
     __device__ static raw enc(T v, uint32_t rnd) {
         if constexpr (SR) {
-            bf16x2 p = {};
+            // the conversion writes the low half and keeps the high half of its first operand:
+            // start from v's own bits, so no register has to be cleared for it
+            bf16x2 p = __builtin_bit_cast(bf16x2, v);
             p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v, rnd, false);
             return __builtin_bit_cast(uint16_t, p[0]);
         } else {
@@ -144,7 +146,7 @@ struct Codec<ST_FP16_DEV> {
     template <bool SR>
     __device__ static raw enc(T v, uint32_t rnd) {
         if constexpr (SR) {
-            f16x2 p = {};
+            f16x2 p = __builtin_bit_cast(f16x2, v);   // as for BF16: no cleared register
             p = __builtin_amdgcn_cvt_sr_f16_f32(p, v, rnd, false);
             return __builtin_bit_cast(uint16_t, p[0]);
         } else {

@@ -15,9 +15,14 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
     return (nblocks & 7u) == 0u ? (bid & 7u) * (nblocks >> 3) + (bid >> 3) : bid;
 }
 
-// Per-population stochastic-rounding bits from one hash per cell.
+// Per-population stochastic-rounding bits from one hash per cell.  Populations 2k and 2k + 1
+// share one hashed word, the odd one rotated by 16 bits: the conversions read a window of at
+// most 16 of the 32 bits (the 16 bits BF16 drops from FP32, the 13 FP16 drops), so the two
+// populations see disjoint bits of the word, and a cell needs ceil(Q / 2) hashes (each two
+// quarter-rate multiplies) instead of Q.
 __device__ __forceinline__ uint32_t pop_bits(uint32_t cell_hash, int a) {
-    return mix32(cell_hash + 0x9e3779b9u * (uint32_t)(a + 1));
+    const uint32_t w = mix32(cell_hash + 0x9e3779b9u * (uint32_t)((a >> 1) + 1));
+    return (a & 1) ? (w >> 16) | (w << 16) : w;
 }
 
 __device__ __forceinline__ int wrap_once(int v, int n) {   // |v| < 2n

@@ -228,16 +228,20 @@ def test_mass_momentum_conservation_gpu():
     assert np.max(np.abs(p1 - p0)) <= 1e-13 * m0
 
 
-VECTOR_CASES = [("D2Q37", 4, (512, 9, 1), "fp32_dev"), ("D2Q37", 2, (256, 7, 1), "fp32"),
-                ("D2Q9", 2, (768, 5, 1), "fp32_dev"), ("D3Q39", 4, (256, 4, 7), "fp32_dev"),
-                ("D2Q16-CK", 3, (512, 9, 1), "fp32_dev"), ("D2Q17", 3, (256, 8, 1), "fp32"),
-                ("D2Q21", 3, (256, 8, 1), "fp32_dev")]
+VECTOR_CASES = [("D2Q37", 4, (512, 9, 1), "fp32_dev", False), ("D2Q37", 2, (256, 7, 1), "fp32", False),
+                ("D2Q9", 2, (768, 5, 1), "fp32_dev", False), ("D3Q39", 4, (256, 4, 7), "fp32_dev", False),
+                ("D2Q16-CK", 3, (512, 9, 1), "fp32_dev", False), ("D2Q17", 3, (256, 8, 1), "fp32", False),
+                ("D2Q21", 3, (256, 8, 1), "fp32_dev", False), ("D3Q39", 4, (256, 4, 7), "bf16_dev", True),
+                ("D3Q39", 4, (256, 5, 6), "fp16_dev", True), ("D2Q37", 4, (512, 9, 1), "bf16_dev", False),
+                ("D2Q9", 2, (256, 6, 1), "fp16_dev", True)]
 
 
-@pytest.mark.parametrize("lattice,N,grid,storage", VECTOR_CASES)
-def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage):
+@pytest.mark.parametrize("lattice,N,grid,storage,sr", VECTOR_CASES)
+def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage, sr):
     """Every tile, including the two 4-cells-per-thread tiles (nx a multiple of 256, |c_x| <= 4,
-    FP32 storages): against the oracle, and bit for bit against tile 0 (same arithmetic)."""
+    FP32 storages; 16-bit storages have the nine others): against the oracle, and bit for bit
+    against tile 0 (same arithmetic, and with stochastic rounding the same bits for every cell
+    and population)."""
     lbm = need_gpu()
     vs = OL.get(lattice)
     axis = 2 if vs.D == 3 else 1
@@ -246,9 +250,11 @@ def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage):
     r.set_shear_wave(1e-3, axis, rho_noise=1e-6, seed=3)
     r.step(5)
     p = perm(lattice)
-    with lbm.Sim(lattice, N, tau, grid, storage=storage) as s:
-        assert s.tile_count() == 11
-        assert [s.tile_info(t)["vector"] for t in range(11)] == [1] * 9 + [4, 4]
+    tol = 1e-5 if storage.startswith("fp32") else 1e-4
+    with lbm.Sim(lattice, N, tau, grid, storage=storage, stochastic_round=sr, sr_seed=9) as s:
+        n = 11 if storage.startswith("fp32") else 9
+        assert s.tile_count() == n
+        assert [s.tile_info(t)["vector"] for t in range(n)] == ([1] * 9 + [4, 4])[:n]
         ref = None
         for t in range(s.tile_count()):
             s.set_tile(t)
@@ -256,8 +262,8 @@ def test_vector_tiles_match_oracle_and_scalar_tile(lattice, N, grid, storage):
             s.step(5)
             st = s.save_state()
             err = rel_err(s.get_populations(), r.f[p])
-            say(f"{lattice} {grid} {storage} tile {t} {s.tile_info(t)}: {err:.2e}")
-            assert err <= 1e-5
+            say(f"{lattice} {grid} {storage} sr={sr} tile {t} {s.tile_info(t)}: {err:.2e}")
+            assert err <= tol
             if ref is None:
                 ref = st
             else:
@@ -281,6 +287,44 @@ def test_deterministic_and_tile_independent(lattice, grid, storage):
             outs.append(s.save_state())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("storage", ["bf16_dev", "fp16_dev"])
+def test_stochastic_rounding_unbiased_and_pairs_independent(storage):
+    """Every cell's population a is set to the same value a fraction p_a of the way between two
+    neighbouring 16-bit values.  Stochastic rounding must round it up in a fraction p_a of the
+    6000 cells (unbiased), and the up/down decisions of populations 2k and 2k + 1, whose bits
+    come from one hashed word, must be uncorrelated."""
+    lbm = need_gpu()
+    _, _, w = lbm.lbm_lattice_info("D2Q9")
+    ncell = 300 * 20
+    rng = np.random.default_rng(11)
+    p = rng.uniform(0.2, 0.8, 9)
+    lo, step = np.empty(9), np.empty(9)
+    for a in range(9):
+        if storage == "bf16_dev":        # stored: f - w, BF16
+            g = np.float32(1e-3 * (1 + a))
+            g_lo = (np.array([g]).view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)[0]
+            ulp = 2.0 ** (np.floor(np.log2(float(g_lo))) - 7)
+            lo[a], step[a] = float(g_lo), ulp
+        else:                            # stored: (f - w) / w, FP16
+            h_lo = float(np.float16(0.01 * (1 + a)))
+            ulp = 2.0 ** (np.floor(np.log2(h_lo)) - 10)
+            lo[a], step[a] = h_lo * w[a], ulp * w[a]
+    f = np.repeat((w + lo + p * step)[:, None], ncell, axis=1)
+    with lbm.Sim("D2Q9", 2, 1.0, (300, 20, 1), storage=storage, stochastic_round=True, sr_seed=5) as s:
+        s.set_populations(f)
+        g = s.get_populations() - w[:, None]
+    up = (g - lo[:, None]) > 0.5 * step[:, None]
+    assert np.all(np.isclose(g, lo[:, None], rtol=1e-6, atol=0) | np.isclose(g, (lo + step)[:, None], rtol=1e-6, atol=0))
+    frac = up.mean(axis=1)
+    sigma = np.sqrt(p * (1 - p) / ncell)
+    assert np.all(np.abs(frac - p) < 5 * sigma), (frac, p)
+    for k in range(4):
+        r = np.corrcoef(up[2 * k], up[2 * k + 1])[0, 1]
+        assert abs(r) < 0.06, (k, r)
+    say(f"SR {storage}: up-fractions within {np.max(np.abs(frac - p) / sigma):.1f} sigma, pair correlations "
+        f"{[round(float(np.corrcoef(up[2 * k], up[2 * k + 1])[0, 1]), 3) for k in range(4)]}")
 
 
 def test_checkpoint_resume_bit_exact():
