@@ -20,12 +20,17 @@ inline int rdvm_threads_per_cell(int nw) {
     while (P > 1 && P * nw > kRdvmBlock) P >>= 1;
     return P;
 }
-// Velocities per thread, rounded up to a kernel variant: 4, 8, 16 or 32 (P >= 2, M <= 64).
+// Velocity slots per thread of the kernel variants (those up to 8 keep their coefficients in
+// registers and read every slot; padded slots cost LDS reads, hence the close spacing).
+constexpr int kRdvmVariants = 6;
+constexpr int kRdvmK[kRdvmVariants] = {4, 5, 6, 8, 16, 32};
+// Velocities per thread, rounded up to a kernel variant (P >= 2 and M <= 64, so at most 32).
 inline int rdvm_variant(int M, int nw) {
     const int P = rdvm_threads_per_cell(nw), k = (M + P - 1) / P;
-    return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+    for (int g = 0; g < kRdvmVariants; ++g)
+        if (k <= kRdvmK[g]) return kRdvmK[g];
+    return kRdvmK[kRdvmVariants - 1];
 }
-constexpr int kRdvmVariants = 4;
 
 struct RdvmInst {
     int32_t M, nw, P;     // velocities, cells, threads per cell
@@ -46,14 +51,20 @@ struct RdvmArgs {
     int64_t steps;
     int32_t record;       // record after every `record` steps of this launch (0 = never)
     int32_t nrec;         // records per instance in this launch
+    int32_t two;          // two state buffers in LDS (rdvm_two_buffers of the largest instance)
 };
 
+constexpr size_t kRdvmMaxLds = 160 * 1024;   // LDS per workgroup (gfx950)
+constexpr int kRdvmTf = kRdvmBlock;           // force time factors tabulated at once (one per thread)
+
 // One workgroup per instance of the list `index` (count entries), all of kernel variant K;
-// lds_bytes = rdvm_lds_bytes(largest M * N_w, largest M).
-// LDS: the state, the coefficients, two sums per wave and the force time factor.
-inline size_t rdvm_lds_bytes(size_t values, int M) {
-    return sizeof(double) * (values + 4 * (size_t)M + 2 * (kRdvmBlock / 64) + 1);
+// lds_bytes = rdvm_lds_bytes(largest M * N_w, largest M, a.two).
+// LDS: the state (two buffers when they fit, so that a step needs one barrier), the
+// coefficients, two sums per wave and the force time factors of the next kRdvmTf steps.
+inline size_t rdvm_lds_bytes(size_t values, int M, bool two) {
+    return sizeof(double) * ((two ? 2 : 1) * values + 4 * (size_t)M + 2 * (kRdvmBlock / 64) + kRdvmTf);
 }
+inline bool rdvm_two_buffers(size_t values, int M) { return rdvm_lds_bytes(values, M, true) <= kRdvmMaxLds; }
 hipError_t launch_rdvm(int K, const RdvmArgs &a, const int32_t *index, uint32_t count, size_t lds_bytes,
                        hipStream_t s);
 hipError_t rdvm_allow_lds(size_t lds_bytes);

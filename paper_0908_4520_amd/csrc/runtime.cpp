@@ -1402,9 +1402,10 @@ struct lbm_rdvm {
     std::vector<RdvmInst> desc;
     RdvmInst *d_inst = nullptr;
     int32_t *d_index = nullptr;             // instance indices grouped by kernel variant
-    int group_first[kRdvmVariants + 1] = {};  // variant 4 << g: d_index[group_first[g] .. group_first[g+1])
+    int group_first[kRdvmVariants + 1] = {};  // variant kRdvmK[g]: d_index[group_first[g] .. group_first[g+1])
     double *d_nodes = nullptr, *d_tabs = nullptr, *d_state = nullptr, *d_log = nullptr;
     size_t state_elems = 0, log_cap = 0, lds_bytes = 0;
+    bool two = false;                      // two state buffers fit in LDS
     int64_t nstep = 0;
 };
 
@@ -1481,7 +1482,7 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
     for (int g = 0; g < kRdvmVariants; ++g) {
         group_first[g] = (int)index.size();
         for (int i = 0; i < count; ++i)
-            if (rdvm_variant(inst[i].nodes, inst[i].cells) == (4 << g)) index.push_back(i);
+            if (rdvm_variant(inst[i].nodes, inst[i].cells) == kRdvmK[g]) index.push_back(i);
     }
     group_first[kRdvmVariants] = (int)index.size();
     lbm_rdvm *r = new lbm_rdvm();
@@ -1491,7 +1492,8 @@ lbm_status lbm_rdvm_create(lbm_rdvm **out, const lbm_rdvm_instance *inst, int32_
     r->inst.assign(inst, inst + count);
     r->desc = desc;
     r->state_elems = state;
-    r->lds_bytes = rdvm_lds_bytes(maxv, maxm);
+    r->two = rdvm_two_buffers(maxv, maxm);
+    r->lds_bytes = rdvm_lds_bytes(maxv, maxm, r->two);
     for (int g = 0; g <= kRdvmVariants; ++g) r->group_first[g] = group_first[g];
     hipError_t e = rdvm_allow_lds(r->lds_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->d_inst, sizeof(RdvmInst) * desc.size());
@@ -1552,9 +1554,10 @@ lbm_status lbm_rdvm_run(lbm_rdvm *r, int64_t steps, int32_t record_every, double
     a.steps = steps;
     a.record = nrec > 0 ? record_every : 0;
     a.nrec = nrec;
+    a.two = r->two ? 1 : 0;
     for (int g = 0; g < kRdvmVariants; ++g) {
         const int n = r->group_first[g + 1] - r->group_first[g];
-        if (n > 0) HIP_TRY(launch_rdvm(4 << g, a, r->d_index + r->group_first[g], (uint32_t)n, r->lds_bytes, r->stream));
+        if (n > 0) HIP_TRY(launch_rdvm(kRdvmK[g], a, r->d_index + r->group_first[g], (uint32_t)n, r->lds_bytes, r->stream));
     }
     r->nstep += steps;
     if (nrec > 0 && (velocity || stress)) {

@@ -28,13 +28,20 @@ def _oracle_series(inst, steps, every):
     return np.array(u), np.array(s), r
 
 
-def test_mixed_instances_match_oracle():
+# Small enough (at most 32 x 128 values) for two state buffers in LDS; 6 and 8 velocity slots
+# per thread (24 and 32 velocities on 128 cells, four lanes per cell).
+MIXED_TWO = [(24, 128, 0.2, 1e-3, 0.25), (32, 128, 0.8, 1e-3, 0.0), (12, 50, 0.1, 1e-3, 0.5),
+             (3, 200, 1.0, 1e-3, 0.3), (20, 128, 0.05, 1e-3, 0.25)]
+
+
+@pytest.mark.parametrize("mixed", [MIXED, MIXED_TWO], ids=["one_buffer", "two_buffers"])
+def test_mixed_instances_match_oracle(mixed):
     lbm = need_gpu()
     steps, every = 120, 5
-    with lbm.ReducedDVM(MIXED) as d:
+    with lbm.ReducedDVM(mixed) as d:
         u, s = d.run(steps, every)
-        states = [d.state(i) for i in range(len(MIXED))]
-        for i, inst in enumerate(MIXED):
+        states = [d.state(i) for i in range(len(mixed))]
+        for i, inst in enumerate(mixed):
             dt, om, n = d.info(i)
             assert n == steps
             uo, so, r = _oracle_series(inst, steps, every)
