@@ -29,6 +29,8 @@ struct BatchArgs {
     void *pool;
     const double *sin_tab;
     const double *bw;
+    const float *bwf;           // the same rounded to FP32, per population one 16-byte record
+                                // alpha_x, beta_x, alpha_y, beta_y at bwf[bw_off + 4 a]
     double *amp;                // amplitude log
     const int32_t *cur;         // per instance: buffer holding the state when the launch starts
     int64_t steps;

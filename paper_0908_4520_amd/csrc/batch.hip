@@ -49,6 +49,21 @@ __device__ __forceinline__ typename Codec<S>::raw *inst_buffer(const BatchInst &
     return static_cast<typename Codec<S>::raw *>(a.pool) + in.off + (size_t)which * L::Q * in.pstride;
 }
 
+// Beam-Warming coefficients (alpha_x, beta_x, alpha_y, beta_y) of population i, in the
+// collision's precision: the FP32 table holds the FP64 values rounded to nearest, one 16-byte
+// record per population, so FP32 kernels take one load and no conversion per population.
+template <class T>
+__device__ __forceinline__ void bw_coefs(const BatchArgs &a, uint32_t off, int i, T &ax, T &bx, T &ay, T &by) {
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 c = *reinterpret_cast<const f4 *>(a.bwf + off + 4 * i);
+        ax = c.x, bx = c.y, ay = c.z, by = c.w;
+    } else {
+        ax = a.bw[off + 0 * kMaxQ + i], bx = a.bw[off + 1 * kMaxQ + i];
+        ay = a.bw[off + 2 * kMaxQ + i], by = a.bw[off + 3 * kMaxQ + i];
+    }
+}
+
 // One step for cells [start, start + count) of an instance, one cell per thread (count <= the
 // block size; with nx = 4 the start is a multiple of 4, so quads are whole rows).
 template <class L, int N, int S, bool BW, bool QUAD>
@@ -75,8 +90,8 @@ __device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs 
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr bool px = L::xi[i][0] > 0.0, py = L::xi[i][1] > 0.0;
-            const T ax = (T)a.bw[in.bw_off + 0 * kMaxQ + i], bx = (T)a.bw[in.bw_off + 1 * kMaxQ + i];
-            const T ay = (T)a.bw[in.bw_off + 2 * kMaxQ + i], by = (T)a.bw[in.bw_off + 3 * kMaxQ + i];
+            T ax, bx, ay, by;
+            bw_coefs<T>(a, in.bw_off, i, ax, bx, ay, by);
             const int rows[3] = {y, imod(py ? y - 1 : y + 1, ny), imod(py ? y - 2 : y + 2, ny)};
             const raw *p = src + (size_t)i * ps;
             T xa[3];
@@ -295,7 +310,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
         }
         __syncthreads();
     }
-    const uint32_t xcd = place[0], entry = place[1];
+    // the same for every lane: read into scalar registers, so the descriptors below are loaded once
+    // per wave by the scalar unit and the coefficients enter the arithmetic as scalar operands
+    const uint32_t xcd = __builtin_amdgcn_readfirstlane(place[0]), entry = __builtin_amdgcn_readfirstlane(place[1]);
     const uint32_t c0 = a.wg_first[entry], c1 = a.wg_first[entry + 1];
     auto record = [&](int k, int64_t done) {
         for (uint32_t c = c0; c < c1; ++c) {

@@ -837,6 +837,7 @@ struct lbm_batch {
     size_t pool_bytes = 0;
     double *d_sin = nullptr;
     double *d_bw = nullptr;
+    float *d_bwf = nullptr;
     double *d_amp = nullptr;
     size_t amp_cap = 0;                     // doubles allocated in d_amp
     int form = 0;                           // 0: workgroup per instance, 1: chunks + grid barrier,
@@ -1056,6 +1057,7 @@ BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t 
     a.pool = b->pool;
     a.sin_tab = b->d_sin;
     a.bw = b->d_bw;
+    a.bwf = b->d_bwf;
     a.amp = b->d_amp;
     a.cur = b->d_cur;
     a.steps = steps;
@@ -1175,11 +1177,18 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     if (e == hipSuccess) e = hipMalloc(&b->d_cur, sizeof(int32_t) * count);
     if (e == hipSuccess) e = hipMalloc(&b->d_sin, sizeof(double) * sin_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_bw, sizeof(double) * bw_h.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_bwf, sizeof(float) * bw_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_barrier, sizeof(uint32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&b->d_sync, sizeof(uint32_t) * kSyncWords);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_sin, sin_h.data(), sizeof(double) * sin_h.size(), hipMemcpyHostToDevice, b->stream);
+    std::vector<float> bwf_h(bw_h.size(), 0.0f);   // per population alpha_x, beta_x, alpha_y, beta_y
+    for (int i = 0; i < count; ++i)
+        for (int a = 0; a < kMaxQ; ++a)
+            for (int k = 0; k < 4; ++k)
+                bwf_h[b->desc[i].bw_off + 4 * a + k] = (float)bw_h[b->desc[i].bw_off + k * kMaxQ + a];
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_bw, bw_h.data(), sizeof(double) * bw_h.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_bwf, bwf_h.data(), sizeof(float) * bwf_h.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->pool, 0, b->pool_bytes, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1203,7 +1212,7 @@ void lbm_batch_free(lbm_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
     for (void *p : {b->pool, (void *)b->d_inst, (void *)b->d_order, (void *)b->d_cur, (void *)b->d_sin,
-                    (void *)b->d_bw, (void *)b->d_amp, (void *)b->d_chunks, (void *)b->d_inst_first,
+                    (void *)b->d_bw, (void *)b->d_bwf, (void *)b->d_amp, (void *)b->d_chunks, (void *)b->d_inst_first,
                     (void *)b->d_wg_first, (void *)b->d_wg_chunks, (void *)b->d_barrier, (void *)b->d_abort,
                     (void *)b->d_partials, (void *)b->d_sync})
         if (p) (void)hipFree(p);
