@@ -274,6 +274,12 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f);
 lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block);
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_t *block, double *ms_per_step);
 lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block);
+/* Testing hook of form 2's fallback: plan it for nxcd XCDs (1..16) instead of the number a probe
+ * launch finds (nxcd = 0 restores the probe).  A plan for fewer XCDs than the device has leaves
+ * the workgroups of the other XCDs without a slot; the next lbm_batch_run sees that before any
+ * step, switches to form 1 and runs there (no kernel waits on a missing workgroup).  LBM_EINVAL
+ * for nxcd outside 0..16. */
+lbm_status lbm_batch_plan_xcds(lbm_batch *b, int32_t nxcd);
 /* Total cells and algorithmic bytes per step (2 Q ncell x bytes per value, summed). */
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
 void lbm_batch_free(lbm_batch *b);   /* NULL-safe */

@@ -848,6 +848,7 @@ struct lbm_batch {
     int plan_block = 0, plan_form = 0;
     uint32_t nchunks = 0, nwg = 0;
     int nxcd = 0;                           // XCDs seen by the probe (0: not probed, -1: form 2 unusable)
+    int xcd_force = 0;                      // plan form 2 for this many XCDs instead (testing; 0 = probe)
     uint32_t wg_per_xcd = 0;
     uint32_t *d_sync = nullptr;
     BatchChunk *d_chunks = nullptr;
@@ -978,7 +979,7 @@ lbm_status batch_plan(lbm_batch *b, int block, int form) {
     std::vector<std::vector<uint32_t>> lists;
     uint32_t nwg = 0, per_xcd = 0;
     if (form == 2) {
-        const uint32_t nx = (uint32_t)b->nxcd;
+        const uint32_t nx = (uint32_t)(b->xcd_force > 0 ? b->xcd_force : b->nxcd);
         std::vector<uint32_t> insts(b->count);
         std::vector<double> icost(b->count, 0.0);
         for (int i = 0; i < b->count; ++i) {
@@ -1073,7 +1074,7 @@ BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t 
     a.abort = b->d_abort;
     a.partials = b->d_partials;
     a.sync = b->form == 2 ? b->d_sync : nullptr;
-    a.nxcd = b->nxcd > 0 ? (uint32_t)b->nxcd : 0u;
+    a.nxcd = b->nxcd > 0 ? (uint32_t)(b->xcd_force > 0 ? b->xcd_force : b->nxcd) : 0u;
     a.wg_per_xcd = b->wg_per_xcd;
     return a;
 }
@@ -1380,6 +1381,15 @@ lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
     if (form) *form = b->form;
     if (block) *block = b->block;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_plan_xcds(lbm_batch *b, int32_t nxcd) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (nxcd < 0 || nxcd > (int32_t)kMaxXcd) return fail(LBM_EINVAL, "nxcd must be in [0, %u]", kMaxXcd);
+    b->xcd_force = nxcd;
+    b->plan_block = 0;   // plan again before the next run
+    batch_drop_graph(b);
     return LBM_OK;
 }
 

@@ -93,6 +93,7 @@ SIGNATURES = {
     "lbm_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _I32, _I32, _D]),
     "lbm_batch_set_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_batch_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_plan_xcds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_gauss_hermite": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
@@ -383,6 +384,10 @@ class Batch:
 
     def set_form(self, form: int, block: int):
         _check(_lib.lbm_batch_set_form(self._h, form, block))
+
+    def plan_xcds(self, nxcd: int):
+        """Testing hook: plan form 2 for nxcd XCDs (0 = as probed)."""
+        _check(_lib.lbm_batch_plan_xcds(self._h, nxcd))
 
     def form(self):
         """(form, block) in use (a run can move form 2 to form 1)."""

@@ -111,6 +111,30 @@ def test_xcd_local_form_equals_device_wide_form_on_the_sweep(block):
     say(f"XCD-local form, block {block}: 256 instances x 60 steps bitwise equal to the device-wide form")
 
 
+def test_xcd_local_form_falls_back_when_the_placement_differs():
+    """Form 2 planned for one XCD on a device with several: the workgroups on the other XCDs
+    find no slot, every workgroup leaves before stepping, and the run is redone in form 1 --
+    with exactly the populations and amplitudes of a batch run in form 1 from the start."""
+    import torch
+    lbm = need_gpu()
+    inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, kn, nx, ny in SMALL if not math.isinf(kn)]
+    several = torch.cuda.get_device_properties(0).multi_processor_count > 32
+    with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(1, 256)
+        b.set_form(2, 256)
+        b.plan_xcds(1)
+        amp_a = a.run(30, 10)
+        amp_b = b.run(30, 10)
+        assert b.form() == ((1, 256) if several else (2, 256))
+        assert np.array_equal(amp_a, amp_b)
+        for i in range(len(inst)):
+            assert np.array_equal(a.populations(i), b.populations(i))
+        amp_a = a.run(7, 7)                         # and the batch goes on in form 1
+        amp_b = b.run(7, 7)
+        assert np.array_equal(amp_a, amp_b)
+        say(f"XCD placement mismatch: ran in form {b.form()[0]} instead, results equal")
+
+
 def _linear_series(lat, tau, ny, steps, every):
     vs = OL.get(lat)
     mode = "shift" if vs.on_lattice else "bw2"
