@@ -166,6 +166,14 @@ constexpr double eq_factor() {
 }
 
 // ------------------------------------------------------------------ moments + collision
+// Index of the population with velocity -xi_a (every set here is symmetric under inversion).
+template <class L>
+constexpr int opposite(int a) {
+    for (int b = 0; b < L::Q; ++b)
+        if (L::xi[b][0] == -L::xi[a][0] && L::xi[b][1] == -L::xi[a][1] && L::xi[b][2] == -L::xi[a][2]) return b;
+    return -1;
+}
+
 template <class T>
 struct Moments {
     T d, jx, jy, jz;
@@ -173,15 +181,39 @@ struct Moments {
 
 template <class L, int S, class T>
 __device__ __forceinline__ Moments<T> project(const T (&v)[L::Q]) {
+    // per velocity pair (xi, -xi): the sum feeds the density, the difference the momentum.
+    // Scaled (FP16) storage keeps the per-population sums: the pair form needs more registers
+    // than its row kernel's occupancy target leaves.
     Moments<T> m{T(0), T(0), T(0), T(0)};
+    if constexpr (Codec<S>::scaled) {
+        static_for<L::Q>([&](auto I) {
+            constexpr int a = decltype(I)::value;
+            const T g = T(moment_factor<L, S, a>()) * v[a];
+            m.d += g;
+            if constexpr (L::xi[a][0] != 0.0) m.jx += T(L::xi[a][0]) * g;
+            if constexpr (L::xi[a][1] != 0.0) m.jy += T(L::xi[a][1]) * g;
+            if constexpr (L::D == 3 && L::xi[a][2] != 0.0) m.jz += T(L::xi[a][2]) * g;
+        });
+        return m;
+    }
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
-        constexpr double mf = moment_factor<L, S, a>();
-        const T g = (mf == 1.0) ? v[a] : T(mf) * v[a];
-        m.d += g;
-        if constexpr (L::xi[a][0] != 0.0) m.jx += T(L::xi[a][0]) * g;
-        if constexpr (L::xi[a][1] != 0.0) m.jy += T(L::xi[a][1]) * g;
-        if constexpr (L::D == 3 && L::xi[a][2] != 0.0) m.jz += T(L::xi[a][2]) * g;
+        constexpr int b = opposite<L>(a);
+        static_assert(b >= 0, "velocity set without inversion symmetry");
+        if constexpr (b >= a) {
+            constexpr double mf = moment_factor<L, S, a>();
+            static_assert(mf == moment_factor<L, S, b>(), "opposite velocities with different weights");
+            if constexpr (b == a) {                 // xi = 0
+                m.d += (mf == 1.0) ? v[a] : T(mf) * v[a];
+            } else {
+                const T sum = v[a] + v[b], dif = v[a] - v[b];
+                const T gs = (mf == 1.0) ? sum : T(mf) * sum, gd = (mf == 1.0) ? dif : T(mf) * dif;
+                m.d += gs;
+                if constexpr (L::xi[a][0] != 0.0) m.jx += T(L::xi[a][0]) * gd;
+                if constexpr (L::xi[a][1] != 0.0) m.jy += T(L::xi[a][1]) * gd;
+                if constexpr (L::D == 3 && L::xi[a][2] != 0.0) m.jz += T(L::xi[a][2]) * gd;
+            }
+        }
     });
     return m;
 }
@@ -203,14 +235,6 @@ constexpr double rounded_momentum_sum() {   // sum_a w_a xi_ax^2 (the same for e
 // Relax the Q values in place; omega = 1/tau (0 = collisionless).  With FORCED, Gx is the
 // body force times dt at this cell and sigma receives the physical shear stresses
 // sum_a xi_ax xi_ay (f_a - f^eq_a) and, in 3-D, sum_a xi_ax xi_az (f_a - f^eq_a).
-// Index of the population with velocity -xi_a (every set here is symmetric under inversion).
-template <class L>
-constexpr int opposite(int a) {
-    for (int b = 0; b < L::Q; ++b)
-        if (L::xi[b][0] == -L::xi[a][0] && L::xi[b][1] == -L::xi[a][1] && L::xi[b][2] == -L::xi[a][2]) return b;
-    return -1;
-}
-
 // Relaxation towards the N-th order equilibrium v^eq_a = e_a (P(s_a) + D0 + D1 s_a), with
 // P(s) = C0 + C1 s + C2 s^2 + C3 s^3 + C4 s^4 (terms up to order N) and the conservation
 // corrections D0, D1 added to the non-equilibrium difference, where FP32 still resolves them.
