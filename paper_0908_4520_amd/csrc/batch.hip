@@ -64,6 +64,15 @@ __device__ __forceinline__ void bw_coefs(const BatchArgs &a, uint32_t off, int i
     }
 }
 
+// Largest |c| over the velocity set's components.
+template <class L>
+constexpr int max_c() {
+    int m = 0;
+    for (int i = 0; i < L::Q; ++i)
+        for (int d = 0; d < L::D; ++d) m = L::c[i][d] > m ? L::c[i][d] : (-L::c[i][d] > m ? -L::c[i][d] : m);
+    return m;
+}
+
 // One step for cells [start, start + count) of an instance, one cell per thread (count <= the
 // block size; with nx = 4 the start is a multiple of 4, so quads are whole rows).
 template <class L, int N, int S, bool BW, bool QUAD>
@@ -81,11 +90,21 @@ __device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs 
     const int x = (int)(cell % (uint32_t)nx), y = (int)(cell / (uint32_t)nx);
     T v[L::Q];
     if constexpr (!BW) {
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny);
-            v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
-        });
+        // grids at least max|c| wide and high (a uniform condition, so a scalar branch): one
+        // conditional add or subtract wraps an index; smaller ones take the true modulo
+        if (nx >= max_c<L>() && ny >= max_c<L>()) {
+            static_for<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const int xs = wrap_once(x - L::c[i][0], nx), ys = wrap_once(y - L::c[i][1], ny);
+                v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
+            });
+        } else {
+            static_for<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny);
+                v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
+            });
+        }
     } else {
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
