@@ -214,3 +214,36 @@ def test_forced_periodic_response(lattice, N, kn, phi, nw, storage):
         f"stress {s_fit:.5e} ({ds:.1e}); |u| Kn/A = {abs(u_fit) * kn / amp:.4f}, "
         f"lag {-math.degrees(math.atan2(u_fit.imag, u_fit.real)):.2f} deg, n = {n_first}..{n_last}")
     assert du <= 1e-4 and ds <= 1e-4
+
+
+def test_forced_d2q37_4096sq_bench_configuration():
+    """The benchmark's forced workload: D2Q37, N = 4, FP32 deviations, 4096 x 4096, Kn = 0.1,
+    body force amplitude 1e-3 at frequency 0.25 on the shear wave u0 = 1e-3, in the autotuned
+    tile, 200 steps.  The state stays uniform along x, so the oracle on one 1 x 4096 column is
+    the exact reference: the velocity and stress projections every 20 steps within 1e-5 of
+    their scale, and sampled columns' populations within 1e-5."""
+    lbm = need_gpu()
+    vs = OL.get("D2Q37")
+    tau = lbm.lbm_tau_from_kn("D2Q37", 0.1, 4096)
+    r = ob.BGK("D2Q37", 4, tau, (1, 4096, 1))
+    r.set_shear_wave(1e-3, 1)
+    r.set_force(1e-3, 0.25, 1)
+    worst_a = worst_s = 0.0
+    with lbm.Sim("D2Q37", 4, tau, (4096, 4096, 1), storage="fp32_dev") as s:
+        s.set_force(1e-3, 0.25, 1)
+        s.set_shear_wave(1e-3, 1)
+        tile, _ = s.autotune(3)
+        s.set_shear_wave(1e-3, 1)
+        assert s.step_count() == 0
+        for _ in range(10):
+            s.step(20)
+            r.step(20)
+            a_gpu, a_ref = np.array(s.shear_amplitude(1)), np.array(r.shear_amplitude(1))
+            s_gpu, s_ref = np.array(s.shear_stress_amplitude()), np.array(r.stress_amplitude())
+            worst_a = max(worst_a, float(np.max(np.abs(a_gpu - a_ref))) / max(abs(a_ref).max(), 1e-30))
+            worst_s = max(worst_s, float(np.max(np.abs(s_gpu - s_ref))) / _stress_scale(vs, 1, r.f))
+        f = s.get_populations().reshape(37, 4096, 4096)
+    fcol = r.f[perm("D2Q37")]
+    f_err = max(float(np.max(np.abs(f[:, :, x] - fcol) / np.abs(fcol))) for x in (0, 1, 2047, 4095))
+    say(f"forced D2Q37 4096^2 tile {tile}: velocity {worst_a:.2e}, stress {worst_s:.2e}, columns {f_err:.2e}")
+    assert worst_a <= 1e-5 and worst_s <= 1e-5 and f_err <= 1e-5
