@@ -154,3 +154,26 @@ def test_d3q39_512cubed_decay_rate(d3q39_column_oracle, storage, sr, tol):
         assert rel <= tol
     else:
         assert rel <= 1.0   # reported only
+
+
+@pytest.mark.parametrize("lattice,N", [("D2Q16-CK", 3), ("D2Q17", 3), ("D2Q21", 3), ("D2Q25-CK", 4)])
+def test_table1_sets_4096sq_bench_configuration(lattice, N):
+    """The benchmark's Table-1 workloads: 4096 x 4096, FP32 deviations, Kn = 0.1, in the
+    autotuned tile, 100 steps: the amplitude series within 1e-5 A0 of the oracle on one
+    1 x 4096 column (exact for the x-uniform wave) and sampled columns within 1e-5."""
+    lbm = need_gpu()
+    tau = lbm.lbm_tau_from_kn(lattice, 0.1, 4096)
+    ref = ob.BGK(lattice, N, tau, (1, 4096, 1))
+    ref.set_shear_wave(A0, 1)
+    a_ref, _ = _series_oracle(ref, 1, 100, 20)
+    with lbm.Sim(lattice, N, tau, (4096, 4096, 1), storage="fp32_dev") as s:
+        s.set_shear_wave(A0, 1)
+        tile, _ = s.autotune(3)
+        s.set_shear_wave(A0, 1)
+        a_gpu, _ = _series_gpu(s, 1, 100, 20)
+        f = s.get_populations().reshape(s.Q, 4096, 4096)
+    err = float(np.max(np.abs(a_gpu - a_ref))) / A0
+    fcol = ref.f[perm(lattice)]
+    f_err = max(float(np.max(np.abs(f[:, :, x] - fcol) / np.abs(fcol))) for x in (0, 1, 2047, 4095))
+    say(f"{lattice} 4096^2 tile {tile}: max |dA|/A0 {err:.2e}, columns {f_err:.2e}")
+    assert err <= 1e-5 and f_err <= 1e-5
