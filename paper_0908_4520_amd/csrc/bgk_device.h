@@ -235,43 +235,6 @@ constexpr double rounded_momentum_sum() {   // sum_a w_a xi_ax^2 (the same for e
 // Relax the Q values in place; omega = 1/tau (0 = collisionless).  With FORCED, Gx is the
 // body force times dt at this cell and sigma receives the physical shear stresses
 // sum_a xi_ax xi_ay (f_a - f^eq_a) and, in 3-D, sum_a xi_ax xi_az (f_a - f^eq_a).
-// Relaxation towards the N-th order equilibrium v^eq_a = e_a (P(s_a) + D0 + D1 s_a), with
-// P(s) = C0 + C1 s + C2 s^2 + C3 s^3 + C4 s^4 (terms up to order N) and the conservation
-// corrections D0, D1 added to the non-equilibrium difference, where FP32 still resolves them.
-// A velocity and its opposite share s up to sign, so P(+-s) = E(s^2) +- s O(s^2) takes one dot
-// product, one square and the even and odd parts once per pair.
-template <class L, int N, int S, class T>
-__device__ __forceinline__ void relax_pairs(T (&v)[L::Q], T omega, T ux, T uy, T uz, T C0, T C1, T C2, T C3, T C4,
-                                            T D0, T D1) {
-    static_for<L::Q>([&](auto I) {
-        constexpr int a = decltype(I)::value;
-        constexpr int b = opposite<L>(a);
-        static_assert(b >= 0, "velocity set without inversion symmetry");
-        if constexpr (b >= a) {
-            T s = T(0);
-            if constexpr (L::xi[a][0] != 0.0) s += T(L::xi[a][0]) * ux;
-            if constexpr (L::xi[a][1] != 0.0) s += T(L::xi[a][1]) * uy;
-            if constexpr (L::D == 3 && L::xi[a][2] != 0.0) s += T(L::xi[a][2]) * uz;
-            const T t = s * s;
-            T E = C0, O = C1;                       // even part, odd part / s
-            if constexpr (N == 2) E = C0 + t * C2;
-            if constexpr (N == 3) { E = C0 + t * C2; O = C1 + t * C3; }
-            if constexpr (N == 4) { E = C0 + t * (C2 + t * C4); O = C1 + t * C3; }
-            const T so = s * O, sd = s * D1;
-            constexpr double ea = eq_factor<L, S, a>();
-            const T pa = E + so, ca = D0 + sd;
-            const T na = ea == 1.0 ? (pa - v[a]) + ca : (T(ea) * pa - v[a]) + T(ea) * ca;
-            v[a] = v[a] + omega * na;
-            if constexpr (b != a) {
-                constexpr double eb = eq_factor<L, S, b>();
-                const T pb = E - so, cb = D0 - sd;
-                const T nb = eb == 1.0 ? (pb - v[b]) + cb : (T(eb) * pb - v[b]) + T(eb) * cb;
-                v[b] = v[b] + omega * nb;
-            }
-        }
-    });
-}
-
 template <class L, int N, int S, class T, bool FORCED>
 __device__ __forceinline__ void collide_impl(T (&v)[L::Q], T omega, T Gx, T (&sigma)[2]) {
     static_assert(N >= 1 && N <= 4, "Hermite order 1..4");
@@ -300,10 +263,6 @@ __device__ __forceinline__ void collide_impl(T (&v)[L::Q], T omega, T Gx, T (&si
     const T rG = rho * Gx, rGu = rho * Gx * ux, b0 = T(1) - T(0.5) * q;
     const T kf = T(1) - T(0.5) * omega;
     T sxy = T(0), sxz = T(0);
-    if constexpr (!FORCED) {
-        relax_pairs<L, N, S, T>(v, omega, ux, uy, uz, C0, C1, C2, C3, C4, D0, D1);
-        return;
-    }
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
         T s = T(0);

@@ -198,3 +198,4 @@ def test_kn_sweep_256_instances_5000_steps():
         worst_oracle = max(worst_oracle, err)
         say(f"Kn sweep instance {i} {lat} ny={ny} tau={tau:.5g}: |dA|/A0 vs oracle {err:.2e} (oracle vs linear {lin_err:.2e})")
     assert worst_oracle <= 1e-5
+    assert max(gam_err)[0] <= 1e-4          # the decay-rate accuracy the FP32 batch is held to
