@@ -153,7 +153,7 @@ def test_kn_sweep_256_instances_5000_steps():
     log-uniform in [0.01, 10], nx = 4), FP32 deviations, 5000 steps, amplitude every 50 steps.
     Every series against the linear single-mode prediction (O(u0^2) and FP32 tolerance
     2e-5 A0); a sample of 12 instances against the oracle itself (1 x ny column, exact for
-    x-uniform data); decay rates where the amplitude decays monotonically."""
+    x-uniform data); decay rates, where the amplitude decays monotonically, within 1e-4."""
     from paper_0908_4520_amd import workloads
     lbm = need_gpu()
     w = workloads.batch_instances(0, 256)
