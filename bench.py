@@ -87,6 +87,28 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
                     bytes_per_step=s.bytes_per_step, ncell=s.ncell)
 
 
+def run_single_instance(lbm, torch, stream, steps=2000):
+    """The 4 x 64 D2Q9 FP64 wave (256 cells) as a batch of one instance: the step loop runs on
+    the device in one persistent launch instead of one launch per step."""
+    tau = lbm.lbm_tau_from_kn("D2Q9", 0.1, 64)
+    with lbm.Batch([("D2Q9", 2, tau, (4, 64), 1e-3)], storage="fp64", stream=stream.cuda_stream) as b:
+        form, block, _ = b.autotune(20)
+        b.reset()
+        b.run(10, 10, record=False)                   # warm-up (captures the graph)
+        b.reset()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        b.run(steps, steps, record=False)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        return dict(ms_per_step=ms / steps, mlups=b.cells * steps / (ms * 1e-3) / 1e6,
+                    gbs=b.bytes_per_step * steps / (ms * 1e-3) / 1e9, cells=b.cells, steps=steps,
+                    form=form, block=block, bytes_per_step=b.bytes_per_step)
+
+
 def run_batch(lbm, torch, stream, steps=5000, record_every=50):
     """The Kn sweep: 256 shear-wave instances (seed 0) in one persistent launch per run."""
     from paper_0908_4520_amd import workloads
@@ -268,6 +290,11 @@ def main():
             r = run_variant(lbm, torch, stream, steps=steps, warmup=5, **kw)
             variants[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             log(f"  {r['ms_per_step']:.4f} ms/step, {r['mlups']:.0f} MLUPS, {r['gbs']:.0f} GB/s")
+        log("timing D2Q9 4x64 FP64 as one persistent instance ...")
+        r = run_single_instance(lbm, torch, stream)
+        variants["D2Q9_4x64_N2_fp64_one_persistent_instance"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                                                 for k, v in r.items()}
+        log(f"  {r['ms_per_step']:.5f} ms/step, {r['mlups']:.0f} MLUPS (form {r['form']}, block {r['block']})")
         log("timing the 256-instance batch (5000 steps) ...")
         r = run_batch(lbm, torch, stream)
         variants["batch_256_instances_5000_steps_fp32_dev"] = {k: (round(v, 4) if isinstance(v, float) else v)
