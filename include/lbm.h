@@ -229,9 +229,9 @@ lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, i
 /* ---- Batches: many independent shear-wave instances advanced together (a Kn sweep).
  * Every instance is a decaying standing shear wave (as lbm_set_shear_wave with no density
  * noise) on its own periodic nx x ny grid with its own velocity set, Hermite order and tau.
- * lbm_batch_run advances all of them by `steps` steps in one persistent kernel launch (each
- * instance owned by one workgroup, the step loop on the device), replayed from a captured
- * HIP graph, and records each instance's sine amplitude of u_x (as lbm_shear_amplitude,
+ * lbm_batch_run advances all of them by `steps` steps in one persistent kernel launch (the
+ * step loop on the device; an instance owned by one workgroup or cut over several, by the
+ * form below), replayed from a captured HIP graph, and records each instance's sine amplitude of u_x (as lbm_shear_amplitude,
  * wave along y) every record_every steps.  Supported: 2-D sets D2Q9, D2Q37 (exact shift),
  * D2Q16_GH, D2Q36_GH (Beam-Warming advection at o->cfl); eq_order 1..4; storage
  * LBM_FP32_DEV or LBM_FP64; wave_axis 1; nz = 1. */
