@@ -91,6 +91,15 @@ typedef struct {
     void *hip_stream;         /* hipStream_t to enqueue on; NULL = null stream */
     int32_t check_every;      /* >0: lbm_step checks the state for NaN/Inf every this many steps */
     int32_t tile;             /* kernel tile choice (0 = autotuned / default); see lbm_tile_count */
+    /* Caller-owned population buffers (both NULL by default: the simulation allocates and frees
+     * its own).  If given, both must be distinct device allocations of the current HIP device,
+     * 16-byte aligned, each of at least dev_buf_bytes >= Q * ncell * (bytes per stored value)
+     * bytes (lbm_state_bytes); they must not overlap and must outlive the simulation, which uses
+     * them as its two buffers of the stored state f* (section 2.2, Eq. 2order) and never frees
+     * them.  Their contents are undefined between calls (the step alternates between them; the
+     * current one is the one lbm_save_state copies).  Batches do not take them. */
+    void *dev_buf[2];
+    int64_t dev_buf_bytes;
 } lbm_opts;
 
 typedef struct lbm_sim lbm_sim;
@@ -116,9 +125,11 @@ double lbm_time_step(lbm_lattice lat, lbm_move move, int32_t wavelength_cells, d
 
 /* Create a simulation with the default options.  eq_order N in 1..4; tau > 1/2 (INFINITY
  * means collisionless, omega = 0); every grid dimension >= 1; nz = 1 for 2-D sets.
- * Allocates two population buffers on the current HIP device.  The state is zero until
- * one of the set calls below.  A quadrature degree below 2N (section 2.1) is allowed;
- * lbm_warnings() then reports LBM_WARN_QUADRATURE. */
+ * Allocates two population buffers on the current HIP device, unless o->dev_buf gives them
+ * (LBM_EINVAL if only one is given, if they are not device memory of the current device, are
+ * misaligned, overlap or are smaller than needed).  The state is zero until one of the set
+ * calls below.  A quadrature degree below 2N (section 2.1) is allowed; lbm_warnings() then
+ * reports LBM_WARN_QUADRATURE. */
 lbm_status lbm_init(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g);
 lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double tau, lbm_grid g,
                        const lbm_opts *o);
@@ -183,6 +194,11 @@ lbm_status lbm_totals(lbm_sim *s, double *mass, double *mom);
  * (encodes into the storage format, rounding as configured; resets nothing else). */
 lbm_status lbm_get_populations(lbm_sim *s, double *f);
 lbm_status lbm_set_populations(lbm_sim *s, const double *f);
+/* Decoded FP64 populations of `count` listed cells (cell = x + nx (y + ny z), each in
+ * [0, ncell)), as lbm_get_populations computes them: f[a * count + k] is population a of
+ * cells[k].  For inspecting grids too large to copy whole.  LBM_EINVAL for a cell out of
+ * range (nothing is copied). */
+lbm_status lbm_get_cells(lbm_sim *s, const int64_t *cells, int64_t count, double *f);
 /* Restore the step counter together with lbm_set_populations (checkpoint resume). */
 lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
 
@@ -248,9 +264,11 @@ typedef struct lbm_batch lbm_batch;
 
 /* Allocates every instance's two population buffers in one device pool and initialises
  * each instance to its shear wave at step 0.  o may be NULL (storage LBM_FP32_DEV, cfl 0.5);
- * o->hip_stream NULL means the batch creates its own stream (graph capture needs one). */
+ * o->hip_stream NULL means the batch creates its own stream (graph capture needs one);
+ * o->dev_buf must be NULL (LBM_EINVAL otherwise). */
 lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t count, const lbm_opts *o);
-/* Every instance back to its shear wave at step 0. */
+/* Every instance back to its shear wave at step 0.  Also the way out of the undefined state a
+ * barrier timeout leaves (see lbm_batch_set_form). */
 lbm_status lbm_batch_reset(lbm_batch *b);
 /* Advance every instance by steps >= 0 steps.  If amp is non-NULL it receives, per instance
  * in input order, steps / record_every + 1 amplitudes (before the first step, then after
@@ -262,9 +280,13 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f);
 /* Three persistent forms: form 0 gives each instance one workgroup for the whole run (no
  * synchronisation across CUs; the largest instance bounds the run time); form 1 cuts every
  * instance into chunks of one cell per thread, spreads them over a grid that is resident at
- * once, and meets at a device-wide barrier after every step (if the barrier's bounded wait
- * expires, the run stops and returns LBM_EDEVICE); form 2 is form 1 with all chunks of an
- * instance on workgroups of one XCD and a barrier per XCD (no data crosses an XCD's L2).
+ * once, and meets at a device-wide barrier after every step; form 2 is form 1 with all chunks of
+ * an instance on workgroups of one XCD and a barrier per XCD (no data crosses an XCD's L2).
+ * Barrier waits are bounded.  If one expires (the workgroups were not resident together), every
+ * workgroup leaves its step loop, the run returns LBM_EDEVICE, and the instances are left partly
+ * stepped: the state is undefined, and lbm_batch_run, lbm_batch_populations, lbm_batch_autotune
+ * and lbm_batch_set_form return LBM_ESTATE until lbm_batch_reset succeeds (lbm_batch_form,
+ * lbm_batch_sizes and lbm_batch_free still work).
  * Form 2 needs the grid's workgroups spread evenly over the XCDs: lbm_batch_set_form returns
  * LBM_EDEVICE if a probe launch finds otherwise, and if a run finds otherwise it changes
  * nothing, switches the batch to form 1 and runs in that form.  Workgroup size 256, 512 or
@@ -280,6 +302,11 @@ lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block);
  * step, switches to form 1 and runs there (no kernel waits on a missing workgroup).  LBM_EINVAL
  * for nxcd outside 0..16. */
 lbm_status lbm_batch_plan_xcds(lbm_batch *b, int32_t nxcd);
+/* Testing hook of the timeout path: bound every barrier wait of the grid forms by `limit` sleeps
+ * of about 50 ns (0 restores the default of 2^26, seconds; larger values are capped there).  A
+ * tiny bound makes waits expire and exercises the undefined-state rule above; every workgroup
+ * still leaves normally. */
+lbm_status lbm_batch_set_spin_limit(lbm_batch *b, uint32_t limit);
 /* Total cells and algorithmic bytes per step (2 Q ncell x bytes per value, summed). */
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
 void lbm_batch_free(lbm_batch *b);   /* NULL-safe */

@@ -43,8 +43,10 @@ struct BatchArgs {
     const uint32_t *wg_chunks;
     uint32_t nwg;               // workgroups of the grid form
     uint32_t nrec;              // amplitudes per instance in this run
-    uint32_t *barrier;          // device-wide barrier counter (zeroed before the launch)
+    uint64_t *barrier;          // device-wide barrier arrivals (zeroed before the launch); 64 bits, so
+                                // steps x workgroups never wraps it
     int32_t *abort;             // 1: a barrier wait exceeded its bound; 2: XCD placement differs from the plan
+    uint32_t spin_limit;        // sleeps a barrier wait may take before it aborts the run
     double *partials;           // per chunk and record: FP64 sums
     // XCD-local grid form: workgroup slot s on XCD x runs the chunks of plan entry x * wg_per_xcd + s
     uint32_t *sync;             // per-XCD counters, see kSyncWords (zeroed before the launch)
@@ -52,8 +54,11 @@ struct BatchArgs {
 };
 
 // Per-XCD counters of the XCD-local form, one 128-byte line each: sync[x * kSyncStride] counts
-// the slots taken on XCD x, sync[(kMaxXcd + x) * kSyncStride] its barrier arrivals.
+// the slots taken on XCD x, the 64-bit word at sync + (kMaxXcd + x) * kSyncStride its barrier
+// arrivals.
 constexpr uint32_t kMaxXcd = 16, kSyncStride = 32, kSyncWords = 2 * kMaxXcd * kSyncStride;
+// Default bound of a barrier wait, in sleeps of ~50 ns: seconds, far beyond any real step.
+constexpr uint32_t kSpinLimit = 1u << 26;
 
 // form 0: one workgroup per instance; form 1: chunks over a resident grid with a device-wide
 // barrier per step; form 2: the same with every instance's chunks on one XCD and a barrier per XCD.

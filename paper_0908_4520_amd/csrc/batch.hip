@@ -233,22 +233,21 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
 }
 
 // ---------------------------------------------------------------- grid form
-constexpr uint32_t kSpinLimit = 1u << 26;   // sleeps of ~50 ns: seconds, far beyond any real step
-
-// Device-wide barrier number `gen` (1, 2, ...).  Returns false if the run was aborted.
-__device__ bool grid_barrier(const BatchArgs &a, uint32_t gen, int *flag) {
+// Device-wide barrier number `gen` (1, 2, ...).  The arrival count is 64-bit: gen * nwg stays
+// exact for any step count.  Returns false if the run was aborted.
+__device__ bool grid_barrier(const BatchArgs &a, uint64_t gen, int *flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();   // release this workgroup's stores to every CU
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = gen * a.nwg;
+        __hip_atomic_fetch_add(a.barrier, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t target = gen * (uint64_t)a.nwg;
         uint32_t spins = 0;
         int ab = 0;
         while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (ab) break;
             __builtin_amdgcn_s_sleep(2);
-            if (++spins >= kSpinLimit) {
+            if (++spins >= a.spin_limit) {
                 __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ab = 1;
                 break;
@@ -271,21 +270,21 @@ __device__ __forceinline__ uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(
 // so that its later loads are served from the L2.  An agent-scope acquire would do as well but
 // also invalidates the XCD's L2, which the other workgroups are still reading from.  Returns
 // false if the run was aborted.
-__device__ bool xcd_barrier(const BatchArgs &a, uint32_t x, uint32_t gen, int *flag) {
+__device__ bool xcd_barrier(const BatchArgs &a, uint32_t x, uint64_t gen, int *flag) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);   // vmcnt(0): this wave's stores are acknowledged by the L2
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t *ctr = a.sync + (kMaxXcd + x) * kSyncStride;
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = gen * a.wg_per_xcd;
+        uint64_t *ctr = reinterpret_cast<uint64_t *>(a.sync + (kMaxXcd + x) * kSyncStride);   // 128-byte aligned
+        __hip_atomic_fetch_add(ctr, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t target = gen * (uint64_t)a.wg_per_xcd;
         uint32_t spins = 0;
         int ab = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             ab = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (ab) break;
             __builtin_amdgcn_s_sleep(1);
-            if (++spins >= 2 * kSpinLimit) {
+            if (++spins >= 2u * a.spin_limit) {   // half-length sleeps: twice the count
                 __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ab = 1;
                 break;
@@ -343,7 +342,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
         }
     };
     if (a.record_first) record(0, 0);
-    uint32_t gen = 0;
+    uint64_t gen = 0;
     for (int64_t step = 0; step < a.steps; ++step) {
         for (uint32_t c = c0; c < c1; ++c) {
             const BatchChunk ch = a.chunks[a.wg_chunks[c]];
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(256) void k_batch_amp(BatchArgs a, uint32_t count) 
 
 __global__ __launch_bounds__(256) void k_batch_reset(BatchArgs a) {
     if (threadIdx.x == 0) {
-        *a.barrier = 0u;
+        *a.barrier = 0ull;
         *a.abort = 0;
     }
     if (a.sync)

@@ -1,7 +1,7 @@
 // kernels.h -- interface between the host runtime and the per-lattice kernel units.
 //
 // Each lattice unit (k_<lattice>.hip) instantiates the templates of kernels_impl.h for
-// its velocity set and fills a table of host launchers; the runtime (api.cpp) picks the
+// its velocity set and fills a table of host launchers; the runtime (runtime.cpp) picks the
 // entry for a simulation's (lattice, Hermite order, storage, rounding).
 #pragma once
 
@@ -14,6 +14,7 @@ namespace lbm {
 
 constexpr int kMaxQ = 40;       // largest Q of any supported set (D3Q39)
 constexpr int kBlock = 256;     // threads per workgroup of every step kernel
+constexpr int kMaxDiagBlocks = 2048;   // workgroups of the diagnostic reduction (grid-stride)
 
 // Where population i of cell (x, r) lives, r = y + ny z the row index: element
 // r * row + i * pop + x of a buffer.  A simulation stores the Q populations of each grid row
@@ -96,6 +97,18 @@ using DiagFn = hipError_t (*)(const DiagArgs &, uint32_t nblocks, hipStream_t);
 using FiniteFn = hipError_t (*)(const void *f, const Layout &lay, uint32_t ncell, int Q, int *flag,
                                 hipStream_t);
 
+// Decoded populations of listed cells: out[a * count + k] = add[a] + mul[a] * f_a(cells[k]).
+struct GatherArgs {
+    const void *f;
+    Layout lay;
+    const uint32_t *cells;
+    uint32_t count;
+    int32_t Q;
+    double *out;
+    double add[kMaxQ], mul[kMaxQ];
+};
+using GatherFn = hipError_t (*)(const GatherArgs &, hipStream_t);
+
 // Everything for one (lattice, N, storage, rounding) combination.
 struct KernelSet {
     int lattice, order, storage, sr;
@@ -119,6 +132,7 @@ struct KernelSet {
     MomentsFn moments;
     DiagFn diag;
     FiniteFn finite;
+    GatherFn gather;
 };
 
 std::vector<KernelSet> &registry();

@@ -460,6 +460,16 @@ __global__ __launch_bounds__(kBlock) void k_decode(const void *fv, Layout lay, u
     out[cell] = add + mul * C::dec64(f[lay.at(a, cell)]);
 }
 
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs g) {
+    using C = Codec<S>;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (uint64_t)g.count * (uint64_t)g.Q) return;
+    const uint32_t a = (uint32_t)(t / g.count), k = (uint32_t)(t - (uint64_t)a * g.count);
+    const auto *f = static_cast<const typename C::raw *>(g.f);
+    g.out[t] = g.add[a] + g.mul[a] * C::dec64(f[g.lay.at((int)a, g.cells[k])]);
+}
+
 template <int S, bool SR>
 __global__ __launch_bounds__(kBlock) void k_encode(void *fv, Layout lay, uint32_t ncell, int a, double add,
                                                    double scale, const double *in, uint32_t key) {
@@ -606,6 +616,12 @@ hipError_t launch_encode(void *f, const Layout &lay, uint32_t ncell, int a, doub
                        in, key);
     return hipGetLastError();
 }
+template <int S>
+hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
+    const uint64_t n = (uint64_t)g.count * (uint64_t)g.Q;
+    hipLaunchKernelGGL((k_gather<S>), dim3((uint32_t)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g);
+    return hipGetLastError();
+}
 template <class L, int S>
 hipError_t launch_moments(const DiagArgs &a, double *rho, double *u, hipStream_t s) {
     const uint32_t ncell = (uint32_t)a.nx * (uint32_t)a.ny * (uint32_t)a.nz;
@@ -659,6 +675,7 @@ KernelSet make_set() {
     k.moments = &launch_moments<L, S>;
     k.diag = &launch_diag<L, S>;
     k.finite = &launch_finite<S>;
+    k.gather = &launch_gather<S>;
     return k;
 }
 

@@ -130,6 +130,8 @@ struct lbm_sim {
     int esize = 0;
     hipStream_t stream = nullptr;
     void *buf[2] = {nullptr, nullptr};
+    bool own_buf = true;        // false: buf[] came from lbm_opts.dev_buf (the caller frees them)
+    int device = 0;             // HIP device current at creation
     int cur = 0;
     int64_t nstep = 0;
     const KernelSet *ks = nullptr;
@@ -294,6 +296,30 @@ lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
     return LBM_OK;
 }
 
+// Caller-owned population buffers (lbm_opts.dev_buf): both given, large enough, aligned for
+// the 16-byte vector accesses, disjoint, and device memory of the current device.
+lbm_status check_dev_buffers(const lbm_opts &o, size_t need) {
+    if (!o.dev_buf[0] || !o.dev_buf[1]) return fail(LBM_EINVAL, "dev_buf: give both buffers or neither");
+    if (o.dev_buf_bytes < 0 || (uint64_t)o.dev_buf_bytes < (uint64_t)need)
+        return fail(LBM_EINVAL, "dev_buf: %lld bytes per buffer given, the state needs %zu", (long long)o.dev_buf_bytes, need);
+    const uintptr_t p0 = (uintptr_t)o.dev_buf[0], p1 = (uintptr_t)o.dev_buf[1];
+    if ((p0 | p1) & 15u) return fail(LBM_EINVAL, "dev_buf: buffers must be 16-byte aligned");
+    if ((p0 < p1 ? p1 - p0 : p0 - p1) < need) return fail(LBM_EINVAL, "dev_buf: the two buffers overlap");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_EDEVICE, "dev_buf: no HIP device");
+    }
+    for (int k = 0; k < 2; ++k) {
+        hipPointerAttribute_t at{};
+        const hipError_t e = hipPointerGetAttributes(&at, o.dev_buf[k]);
+        if (e != hipSuccess) (void)hipGetLastError();
+        if (e != hipSuccess || at.type != hipMemoryTypeDevice || at.device != dev)
+            return fail(LBM_EINVAL, "dev_buf[%d] is not device memory of the current device %d", k, dev);
+    }
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -368,6 +394,12 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     }
     if (move != LBM_MOVE_SHIFT && move != LBM_MOVE_BW2) return fail(LBM_EINVAL, "unknown move %d", (int)move);
     if (o.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+    const size_t state_bytes = (size_t)L->Q * (size_t)ncell * (size_t)elem_size(o.storage);
+    const bool given = o.dev_buf[0] != nullptr || o.dev_buf[1] != nullptr;
+    if (given) {
+        lbm_status st = check_dev_buffers(o, state_bytes);
+        if (st != LBM_OK) return st;
+    }
     const int sr = (o.stochastic_round && (o.storage == LBM_FP16_DEV || o.storage == LBM_BF16_DEV)) ? 1 : 0;
     const KernelSet *ks = find_kernels((int)lat, eq_order, (int)o.storage, sr);
     if (!ks) return fail(LBM_EINVAL, "no kernels for lattice %d order %d storage %d", (int)lat, eq_order, (int)o.storage);
@@ -400,10 +432,17 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
                 s->bwf.beta[d][a] = (float)b;
             }
     }
-    s->diag_blocks = (uint32_t)std::min<size_t>((s->ncell + kBlock - 1) / kBlock, 2048);
-    const size_t bytes = (size_t)L->Q * s->ncell * (size_t)s->esize;
-    hipError_t e = hipMalloc(&s->buf[0], bytes);
-    if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
+    s->diag_blocks = (uint32_t)std::min<size_t>((s->ncell + kBlock - 1) / kBlock, kMaxDiagBlocks);
+    const size_t bytes = state_bytes;
+    hipError_t e = hipGetDevice(&s->device);
+    if (given) {
+        s->own_buf = false;
+        s->buf[0] = o.dev_buf[0];
+        s->buf[1] = o.dev_buf[1];
+    } else {
+        if (e == hipSuccess) e = hipMalloc(&s->buf[0], bytes);
+        if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
+    }
     if (e == hipSuccess) e = hipMalloc(&s->d_partials, sizeof(double) * 6 * s->diag_blocks);
     if (e == hipSuccess) e = hipMalloc(&s->d_result, sizeof(double) * 8);
     if (e == hipSuccess) e = hipMalloc(&s->d_flag, sizeof(int) * 4);
@@ -424,8 +463,11 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
 void lbm_free(lbm_sim *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    for (void *p : {s->buf[0], s->buf[1], (void *)s->d_tab, (void *)s->d_partials, (void *)s->d_result,
-                    (void *)s->d_flag, (void *)s->d_ftab, (void *)s->d_stress})
+    if (s->own_buf)
+        for (void *p : {s->buf[0], s->buf[1]})
+            if (p) (void)hipFree(p);
+    for (void *p : {(void *)s->d_tab, (void *)s->d_partials, (void *)s->d_result, (void *)s->d_flag,
+                    (void *)s->d_ftab, (void *)s->d_stress})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -566,6 +608,39 @@ lbm_status lbm_get_populations(lbm_sim *s, double *f) {
         if (e == hipSuccess) e = hipMemcpyAsync(f + (size_t)a * n, d, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     }
+    (void)hipFree(d);
+    HIP_TRY(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_cells(lbm_sim *s, const int64_t *cells, int64_t count, double *f) {
+    if (!s || (count > 0 && (!cells || !f))) return fail(LBM_EINVAL, "NULL argument");
+    if (count < 0 || count > (int64_t)(0x7fffffff / kMaxQ)) return fail(LBM_EINVAL, "count out of range");
+    if (count == 0) return LBM_OK;
+    std::vector<uint32_t> idx((size_t)count);
+    for (int64_t k = 0; k < count; ++k) {
+        if (cells[k] < 0 || cells[k] >= (int64_t)s->ncell)
+            return fail(LBM_EINVAL, "cell %lld out of range [0, %zu)", (long long)cells[k], s->ncell);
+        idx[(size_t)k] = (uint32_t)cells[k];
+    }
+    GatherArgs g{};
+    g.f = s->buf[s->cur];
+    g.lay = s->lay;
+    g.count = (uint32_t)count;
+    g.Q = s->L->Q;
+    for (int a = 0; a < s->L->Q; ++a) {
+        g.add[a] = is_dev(s->o.storage) ? s->L->w[a] : 0.0;
+        g.mul[a] = is_scaled(s->o.storage) ? s->L->w[a] : 1.0;
+    }
+    const size_t nout = (size_t)count * (size_t)s->L->Q;
+    void *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(uint32_t) * (size_t)count + sizeof(double) * nout + 8));
+    g.cells = static_cast<const uint32_t *>(d);
+    g.out = reinterpret_cast<double *>(static_cast<char *>(d) + ((sizeof(uint32_t) * (size_t)count + 7) & ~(size_t)7));
+    hipError_t e = hipMemcpyAsync(d, idx.data(), sizeof(uint32_t) * (size_t)count, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = s->ks->gather(g, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, g.out, sizeof(double) * nout, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     HIP_TRY(e);
     return LBM_OK;
@@ -853,8 +928,10 @@ struct lbm_batch {
     uint32_t *d_sync = nullptr;
     BatchChunk *d_chunks = nullptr;
     uint32_t *d_inst_first = nullptr, *d_wg_first = nullptr, *d_wg_chunks = nullptr;
-    uint32_t *d_barrier = nullptr;
+    uint64_t *d_barrier = nullptr;
     int32_t *d_abort = nullptr;
+    uint32_t spin_limit = kSpinLimit;       // bound of a barrier wait (sleeps)
+    bool poisoned = false;                  // a barrier wait expired: state undefined until reset
     double *d_partials = nullptr;
     size_t partials_cap = 0;
     // cached graph of one run configuration
@@ -1072,6 +1149,7 @@ BatchArgs batch_args(const lbm_batch *b, int64_t steps, int32_t record, int32_t 
     a.nrec = nrec;
     a.barrier = b->d_barrier;
     a.abort = b->d_abort;
+    a.spin_limit = b->spin_limit;
     a.partials = b->d_partials;
     a.sync = b->form == 2 ? b->d_sync : nullptr;
     a.nxcd = b->nxcd > 0 ? (uint32_t)(b->xcd_force > 0 ? b->xcd_force : b->nxcd) : 0u;
@@ -1102,6 +1180,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     if (opts) o = *opts;
     if (o.storage != LBM_FP32_DEV && o.storage != LBM_FP64)
         return fail(LBM_EINVAL, "batches store LBM_FP32_DEV or LBM_FP64");
+    if (o.dev_buf[0] || o.dev_buf[1]) return fail(LBM_EINVAL, "batches allocate their own pool: dev_buf must be NULL");
     if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1]");
     for (int i = 0; i < count; ++i) {
         const lbm_instance &q = inst[i];
@@ -1179,7 +1258,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     if (e == hipSuccess) e = hipMalloc(&b->d_sin, sizeof(double) * sin_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_bw, sizeof(double) * bw_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_bwf, sizeof(float) * bw_h.size());
-    if (e == hipSuccess) e = hipMalloc(&b->d_barrier, sizeof(uint32_t) * 2);
+    if (e == hipSuccess) e = hipMalloc(&b->d_barrier, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = hipMalloc(&b->d_sync, sizeof(uint32_t) * kSyncWords);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_sin, sin_h.data(), sizeof(double) * sin_h.size(), hipMemcpyHostToDevice, b->stream);
@@ -1223,7 +1302,16 @@ void lbm_batch_free(lbm_batch *b) {
 
 lbm_status lbm_batch_reset(lbm_batch *b) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
-    return batch_init_states(b);
+    lbm_status st = batch_init_states(b);
+    if (st == LBM_OK) b->poisoned = false;
+    return st;
+}
+
+lbm_status lbm_batch_set_spin_limit(lbm_batch *b, uint32_t limit) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    b->spin_limit = limit == 0 ? kSpinLimit : std::min(limit, kSpinLimit);
+    batch_drop_graph(b);
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step) {
@@ -1235,6 +1323,7 @@ lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_pe
 
 lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, double *amp) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
     if (steps < 0 || record_every < 1) return fail(LBM_EINVAL, "steps >= 0 and record_every >= 1 required");
     const int64_t per = amp ? steps / record_every + 1 : 1;
     if (per * (int64_t)b->count > (1ll << 31)) return fail(LBM_EINVAL, "amplitude log too large");
@@ -1282,7 +1371,12 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
         if ((st = lbm_batch_set_form(b, 1, b->block)) != LBM_OK) return st;
         return lbm_batch_run(b, steps, record_every, amp);
     }
-    if (ab) return fail(LBM_EDEVICE, "batch grid barrier timed out: workgroups were not resident together");
+    if (ab) {
+        // the workgroups left the step loop at different steps: the instances are partly stepped
+        b->poisoned = true;
+        return fail(LBM_EDEVICE, "batch grid barrier timed out: workgroups were not resident together; "
+                                 "the state is undefined until lbm_batch_reset");
+    }
     if (steps & 1)
         for (auto &c : b->cur) c ^= 1;
     return LBM_OK;
@@ -1290,6 +1384,7 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
 
 lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
     if (!b || !f) return fail(LBM_EINVAL, "NULL argument");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
     if (index < 0 || index >= b->count) return fail(LBM_EINVAL, "index out of range");
     const BatchInst &d = b->desc[index];
     const LatInfo *L = lat_info(d.lattice);
@@ -1311,6 +1406,7 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
 
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_t *block, double *ms_per_step) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     void *save = nullptr;
     HIP_TRY(hipMalloc(&save, b->pool_bytes));
@@ -1395,6 +1491,7 @@ lbm_status lbm_batch_plan_xcds(lbm_batch *b, int32_t nxcd) {
 
 lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block) {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
     if ((form < 0 || form > 2) || (block != 256 && block != 512 && block != 1024))
         return fail(LBM_EINVAL, "form must be 0, 1 or 2 and block 256, 512 or 1024");
     if (form >= 1) {

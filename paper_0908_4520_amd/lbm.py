@@ -30,7 +30,8 @@ class lbm_grid(ctypes.Structure):
 class lbm_opts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int), ("move", ctypes.c_int), ("cfl", ctypes.c_double),
                 ("stochastic_round", ctypes.c_int32), ("sr_seed", ctypes.c_uint64),
-                ("hip_stream", ctypes.c_void_p), ("check_every", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("hip_stream", ctypes.c_void_p), ("check_every", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("dev_buf", ctypes.c_void_p * 2), ("dev_buf_bytes", ctypes.c_int64)]
 
 
 class lbm_instance(ctypes.Structure):
@@ -73,6 +74,7 @@ SIGNATURES = {
     "lbm_totals": (ctypes.c_int, [_SIM, _D, _D]),
     "lbm_get_populations": (ctypes.c_int, [_SIM, _D]),
     "lbm_set_populations": (ctypes.c_int, [_SIM, _D]),
+    "lbm_get_cells": (ctypes.c_int, [_SIM, _I64, ctypes.c_int64, _D]),
     "lbm_set_step_count": (ctypes.c_int, [_SIM, ctypes.c_int64]),
     "lbm_state_bytes": (ctypes.c_int, [_SIM, _I64]),
     "lbm_save_state": (ctypes.c_int, [_SIM, ctypes.c_void_p, ctypes.c_int64]),
@@ -94,6 +96,7 @@ SIGNATURES = {
     "lbm_batch_set_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_batch_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_plan_xcds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbm_batch_set_spin_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_gauss_hermite": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
@@ -196,7 +199,9 @@ class Sim:
 
     def __init__(self, lattice: str, eq_order: int, tau: float, grid, storage: str = "fp64",
                  move: str = "auto", cfl: float = 0.5, stochastic_round: bool = False, sr_seed: int = 0,
-                 stream=None, check_every: int = 0, tile: int = 0):
+                 stream=None, check_every: int = 0, tile: int = 0, dev_buf=None, dev_buf_bytes: int = 0):
+        """dev_buf = (ptr0, ptr1): caller-owned device buffers of dev_buf_bytes each (for example
+        torch tensors' data_ptr()); they must outlive the Sim."""
         o = lbm_opts_default()
         o.storage = STORAGES[storage]
         o.move = MOVES[move]
@@ -206,6 +211,9 @@ class Sim:
         o.hip_stream = stream
         o.check_every = check_every
         o.tile = tile
+        if dev_buf is not None:
+            o.dev_buf[0], o.dev_buf[1] = dev_buf[0], dev_buf[1]
+            o.dev_buf_bytes = int(dev_buf_bytes)
         g = lbm_grid(*[int(v) for v in grid])
         h = _SIM()
         _check(_lib.lbm_init_ex(ctypes.byref(h), LATTICES[lattice], eq_order, float(tau), g, ctypes.byref(o)))
@@ -282,6 +290,13 @@ class Sim:
     def get_populations(self) -> np.ndarray:
         f = np.empty((self.Q, self.ncell))
         _check(_lib.lbm_get_populations(self._h, _dp(f)))
+        return f
+
+    def get_cells(self, cells) -> np.ndarray:
+        """Decoded populations f[a, k] of the listed cells (linear indices x + nx (y + ny z))."""
+        c = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1)
+        f = np.empty((self.Q, c.size))
+        _check(_lib.lbm_get_cells(self._h, c.ctypes.data_as(_I64), c.size, _dp(f)))
         return f
 
     def set_populations(self, f: np.ndarray):
@@ -388,6 +403,10 @@ class Batch:
     def plan_xcds(self, nxcd: int):
         """Testing hook: plan form 2 for nxcd XCDs (0 = as probed)."""
         _check(_lib.lbm_batch_plan_xcds(self._h, nxcd))
+
+    def set_spin_limit(self, limit: int):
+        """Testing hook: bound of every barrier wait in sleeps (0 = default)."""
+        _check(_lib.lbm_batch_set_spin_limit(self._h, limit))
 
     def form(self):
         """(form, block) in use (a run can move form 2 to form 1)."""

@@ -40,10 +40,13 @@ def test_every_declared_symbol_is_exported_and_bound(lbm):
 
 def test_struct_layouts_match_header(lbm):
     assert ctypes.sizeof(lbm.lbm_grid) == 12
-    # lbm_opts: int, int, double, int32, uint64, void*, int32, int32 with natural alignment
-    assert ctypes.sizeof(lbm.lbm_opts) == 48
+    # lbm_opts: int, int, double, int32, uint64, void*, int32, int32, void*[2], int64 with natural
+    # alignment
+    assert ctypes.sizeof(lbm.lbm_opts) == 72
+    assert lbm.lbm_opts.dev_buf.offset == 48 and lbm.lbm_opts.dev_buf_bytes.offset == 64
     o = lbm.lbm_opts_default()
     assert o.storage == 0 and o.move == 0 and o.cfl == 0.5 and o.hip_stream is None
+    assert o.dev_buf[0] is None and o.dev_buf[1] is None and o.dev_buf_bytes == 0
 
 
 def test_tau_from_kn(lbm):
@@ -164,3 +167,29 @@ def test_reduced_dvm_rejects_invalid_instances_without_device(lbm, inst, msg):
     assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
     with pytest.raises(lbm.LbmError):
         lbm.ReducedDVM([(4, 8, 1.0, 0.0, 0.0)], cfl=1.5)
+
+
+BAD_DEV_BUF = [
+    ((0x1000, None), 1 << 20, "both buffers or neither"),
+    ((None, 0x1000), 1 << 20, "both buffers or neither"),
+    ((0x100000, 0x200000), 100, "bytes per buffer"),
+    ((0x100008, 0x900000), 1 << 20, "16-byte aligned"),
+    ((0x100000, 0x100400), 1 << 20, "overlap"),
+]
+
+
+@pytest.mark.parametrize("bufs,nbytes,msg", BAD_DEV_BUF)
+def test_invalid_caller_buffers_rejected_before_device_work(lbm, bufs, nbytes, msg):
+    """lbm_opts.dev_buf is checked (pairing, size, alignment, overlap) before any HIP call; the
+    addresses here are never dereferenced."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Sim("D2Q9", 2, 1.0, (16, 16, 1), dev_buf=bufs, dev_buf_bytes=nbytes)
+    assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
+
+
+def test_get_cells_validates_before_device_work(lbm):
+    """Out-of-range cells are rejected by the host before any copy (checked on a NULL sim here:
+    the argument checks come first)."""
+    f = np.zeros(9)
+    cells = np.array([0], dtype=np.int64)
+    assert lbm.lib().lbm_get_cells(None, cells.ctypes.data_as(lbm._I64), 1, lbm._dp(f)) == lbm.LBM_EINVAL

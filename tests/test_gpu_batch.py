@@ -199,3 +199,41 @@ def test_kn_sweep_256_instances_5000_steps():
         say(f"Kn sweep instance {i} {lat} ny={ny} tau={tau:.5g}: |dA|/A0 vs oracle {err:.2e} (oracle vs linear {lin_err:.2e})")
     assert worst_oracle <= 1e-5
     assert max(gam_err)[0] <= 1e-4          # the decay-rate accuracy the FP32 batch is held to
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_barrier_timeout_leaves_state_undefined_until_reset(form):
+    """Force the grid forms' bounded barrier wait to expire from the host (a bound of one sleep,
+    on the 256-instance sweep, where one workgroup cannot see thousands of others arrive within
+    one sleep).  Every workgroup still leaves normally; the run reports LBM_EDEVICE, and every
+    call that reads or steps the state reports LBM_ESTATE until lbm_batch_reset.  After the reset
+    (default bound) the batch runs exactly like a fresh one."""
+    from paper_0908_4520_amd import workloads
+    lbm = need_gpu()
+    inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, nx, ny, kn in workloads.batch_instances(0, 256)]
+    with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(form, 256)
+        b.set_form(1, 256)
+        a.set_spin_limit(1)
+        timed_out = False
+        try:
+            a.run(40, 10)
+        except lbm.LbmError as e:
+            assert e.code == lbm.LBM_EDEVICE
+            timed_out = True
+        say(f"form {form} with a one-sleep barrier bound: timed out = {timed_out}")
+        if timed_out:
+            for call in (lambda: a.run(1, 1), lambda: a.populations(0), lambda: a.autotune(2),
+                         lambda: a.set_form(1, 512)):
+                with pytest.raises(lbm.LbmError) as e:
+                    call()
+                assert e.value.code == lbm.LBM_ESTATE
+            assert a.form()[1] == 256
+        a.set_spin_limit(0)
+        a.reset()
+        a.set_form(form, 256)
+        amp_a = a.run(40, 10)
+        amp_b = b.run(40, 10)
+        assert np.array_equal(amp_a, amp_b)
+        for i in (0, 100, 255):
+            assert np.array_equal(a.populations(i), b.populations(i))

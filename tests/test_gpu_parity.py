@@ -378,3 +378,64 @@ def test_full_size_d2q37_sampled_cells():
             worst = max(worst, float(np.max(np.abs(got - ref[p]) / np.abs(ref[p]))))
         say(f"Kn={kn}: worst sampled rel err {worst:.2e}")
         assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32_dev", "bf16_dev", "fp16_dev"])
+def test_get_cells_equals_get_populations(storage):
+    """lbm_get_cells decodes listed cells exactly as lbm_get_populations decodes the whole state."""
+    lbm = need_gpu()
+    grid = (260, 5, 4)
+    with lbm.Sim("D3Q39", 4, 1.1, grid, storage=storage, stochastic_round=storage != "fp64" and storage != "fp32_dev",
+                 sr_seed=3) as s:
+        s.set_shear_wave(1e-3, 2, rho_noise=1e-6, seed=2)
+        s.step(3)
+        f = s.get_populations()
+        cells = np.array([0, 1, 259, 260, 777, 5199, 3 * 1300 + 42, 2 * 1300], dtype=np.int64)
+        g = s.get_cells(cells)
+        assert np.array_equal(g, f[:, cells])
+        assert s.get_cells(np.zeros(0, np.int64)).shape == (39, 0)
+        with pytest.raises(lbm.LbmError) as e:
+            s.get_cells([0, 260 * 5 * 4])
+        assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("storage,lattice,N,grid", [("fp32_dev", "D2Q37", 4, (512, 24, 1)),
+                                                    ("fp64", "D2Q16-GH", 3, (300, 20, 1)),
+                                                    ("fp16_dev", "D3Q39", 4, (256, 4, 6))])
+def test_caller_owned_buffers_bitwise_equal_to_library_owned(storage, lattice, N, grid):
+    """lbm_opts.dev_buf: a simulation whose two buffers of the stored state f* (section 2.2,
+    Eq. 2order) are torch tensors steps bit for bit like one that allocates its own, also
+    after a raw checkpoint round trip; the tensors hold the state, and stay valid after the
+    simulation is freed."""
+    import torch
+    lbm = need_gpu()
+    axis = 2 if lattice == "D3Q39" else 1
+    kw = dict(storage=storage, stochastic_round=storage == "fp16_dev", sr_seed=5)
+    with lbm.Sim(lattice, N, 1.3, grid, **kw) as ref:
+        nbytes = ref.Q * ref.ncell * lbm.STORAGE_BYTES[storage]
+        t = [torch.full((nbytes + 64,), 7, dtype=torch.uint8, device="cuda") for _ in range(2)]
+        torch.cuda.synchronize()
+        with lbm.Sim(lattice, N, 1.3, grid, dev_buf=(t[0].data_ptr(), t[1].data_ptr()),
+                     dev_buf_bytes=nbytes + 64, **kw) as s:
+            for sim in (ref, s):
+                sim.set_shear_wave(1e-3, axis, rho_noise=1e-6, seed=4)
+                sim.step(7)
+            state = s.save_state()
+            assert np.array_equal(ref.save_state(), state)
+            torch.cuda.synchronize()
+            assert np.array_equal(t[1][:nbytes].cpu().numpy(), state)    # 7 steps: buffer 1 is current
+            snap, n = ref.save_state(), ref.step_count()
+            ref.step(6)
+            s.load_state(snap)
+            s.set_step_count(n)
+            s.step(6)
+            assert np.array_equal(ref.save_state(), s.save_state())
+            assert np.array_equal(ref.get_populations(), s.get_populations())
+        torch.cuda.synchronize()
+        assert int(t[0][nbytes:].sum().item()) == 7 * 64     # bytes beyond the state untouched
+        host = np.zeros(nbytes, np.uint8)
+        for bufs, size, msg in [((t[0].data_ptr(), t[1].data_ptr()), nbytes - 8, "bytes per buffer"),
+                                ((host.ctypes.data, t[1].data_ptr()), nbytes, "not device memory")]:
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.Sim(lattice, N, 1.3, grid, dev_buf=bufs, dev_buf_bytes=size, **kw)
+            assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
