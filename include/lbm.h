@@ -187,6 +187,17 @@ lbm_status lbm_moments(lbm_sim *s, double *rho, double *u);
  * with wave-axis index j (the velocity amplitude of section 4); a_cos likewise. */
 lbm_status lbm_shear_amplitude(lbm_sim *s, int32_t wave_axis, double *a_sin, double *a_cos);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops): lbm_shear_amplitude without any allocation and without synchronising.  Enqueues the same
+ * reduction kernels on the simulation's stream and writes a_sin to dev_out[0] and a_cos to
+ * dev_out[1], where dev_out points to two doubles of device memory (bit for bit the values
+ * lbm_shear_amplitude returns).  The reduction's partial sums go to a static scratch array of
+ * the library (about 96 KiB per GPU, held until the process ends; at most 2048 reduction
+ * workgroups, which every simulation satisfies, else LBM_EINVAL); calls that overlap on one GPU,
+ * on any streams, share that array and race.  LBM_EINVAL for NULL pointers or an invalid axis,
+ * LBM_EDEVICE if the scratch could not be located on the simulation's device. */
+lbm_status lbm_shear_amplitude_noalloc(lbm_sim *s, int32_t wave_axis, double *dev_out);
+
 /* Global FP64 sums: mass = sum rho, mom[d] = sum rho u_d (D entries). */
 lbm_status lbm_totals(lbm_sim *s, double *mass, double *mom);
 

@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "lattices.inc"
 #include "lbm.h"
+#include "noalloc.h"
 
 using namespace lbm;
 
@@ -137,8 +138,8 @@ struct lbm_sim {
     const KernelSet *ks = nullptr;
     bool rows_ok = false;       // row-tiled shift kernel is valid for this grid
     int tile = 0;
-    double *d_tab = nullptr;    // sin then cos table of the current wave axis
-    int tab_axis = -1;
+    double *d_tab = nullptr;    // sin(2 pi j / ny), cos(2 pi j / ny) for j < ny, then the same along z
+                                // (3-D sets), made at creation
     double *d_partials = nullptr;
     double *d_result = nullptr;
     int *d_flag = nullptr;
@@ -246,24 +247,24 @@ int tile_count(const lbm_sim *s) {
     return 1;
 }
 
-lbm_status ensure_tables(lbm_sim *s, int axis) {
-    if (s->tab_axis == axis) return LBM_OK;
-    const int nw = axis == 1 ? s->g.ny : s->g.nz;
-    std::vector<double> h(2 * (size_t)nw);
-    for (int j = 0; j < nw; ++j) {
-        const double ph = 2.0 * M_PI * (double)j / (double)nw;
-        h[j] = sin(ph);
-        h[nw + j] = cos(ph);
+// Host values of the wave tables (host libm): for each wave axis (y, then z for 3-D sets)
+// sin(2 pi j / N_w) then cos(2 pi j / N_w), j < N_w.
+std::vector<double> wave_tables(const lbm_sim *s) {
+    std::vector<double> h;
+    for (int axis = 1; axis <= (s->L->D == 3 ? 2 : 1); ++axis) {
+        const int nw = axis == 1 ? s->g.ny : s->g.nz;
+        const size_t o = h.size();
+        h.resize(o + 2 * (size_t)nw);
+        for (int j = 0; j < nw; ++j) {
+            const double ph = 2.0 * M_PI * (double)j / (double)nw;
+            h[o + j] = sin(ph);
+            h[o + nw + j] = cos(ph);
+        }
     }
-    if (s->d_tab) HIP_TRY(hipFree(s->d_tab));
-    s->d_tab = nullptr;
-    s->tab_axis = -1;
-    HIP_TRY(hipMalloc(&s->d_tab, sizeof(double) * h.size()));
-    HIP_TRY(hipMemcpyAsync(s->d_tab, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    s->tab_axis = axis;
-    return LBM_OK;
+    return h;
 }
+const double *sin_table(const lbm_sim *s, int axis) { return s->d_tab + (axis == 1 ? 0 : 2 * (size_t)s->g.ny); }
+const double *cos_table(const lbm_sim *s, int axis) { return sin_table(s, axis) + (axis == 1 ? s->g.ny : s->g.nz); }
 
 lbm_status check_axis(const lbm_sim *s, int axis) {
     if (axis == 1) return LBM_OK;
@@ -271,10 +272,8 @@ lbm_status check_axis(const lbm_sim *s, int axis) {
     return fail(LBM_EINVAL, "wave_axis must be 1 (y) or, for 3-D sets, 2 (z); got %d", axis);
 }
 
-// Runs the diagnostic reduction and copies the 6 sums to host.
-lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
-    lbm_status st = ensure_tables(s, axis);
-    if (st != LBM_OK) return st;
+// Arguments of the diagnostic reduction of the current state along `axis` into `partials`.
+DiagArgs diag_args(const lbm_sim *s, int axis, double *partials) {
     DiagArgs a{};
     a.f = s->buf[s->cur];
     a.nx = s->g.nx;
@@ -282,13 +281,18 @@ lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
     a.nz = s->g.nz;
     a.lay = s->lay;
     a.wave_axis = axis;
-    const int nw = axis == 1 ? s->g.ny : s->g.nz;
-    a.sin_tab = s->d_tab;
-    a.cos_tab = s->d_tab + nw;
-    a.partials = s->d_partials;
+    a.sin_tab = sin_table(s, axis);
+    a.cos_tab = cos_table(s, axis);
+    a.partials = partials;
     a.half_g = 0.5 * force_g_at(s, s->nstep);
     a.force_cos = s->d_ftab;
     a.force_axis = s->f_axis;
+    return a;
+}
+
+// Runs the diagnostic reduction and copies the 6 sums to host.
+lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
+    const DiagArgs a = diag_args(s, axis, s->d_partials);
     HIP_TRY(s->ks->diag(a, s->diag_blocks, s->stream));
     HIP_TRY(diag_final(s->d_partials, s->diag_blocks, 6, s->d_result, s->stream));
     HIP_TRY(hipMemcpyAsync(out, s->d_result, 6 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -443,6 +447,9 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
         if (e == hipSuccess) e = hipMalloc(&s->buf[0], bytes);
         if (e == hipSuccess) e = hipMalloc(&s->buf[1], bytes);
     }
+    const std::vector<double> tabs = wave_tables(s);
+    if (e == hipSuccess) e = hipMalloc(&s->d_tab, sizeof(double) * tabs.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_tab, tabs.data(), sizeof(double) * tabs.size(), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMalloc(&s->d_partials, sizeof(double) * 6 * s->diag_blocks);
     if (e == hipSuccess) e = hipMalloc(&s->d_result, sizeof(double) * 8);
     if (e == hipSuccess) e = hipMalloc(&s->d_flag, sizeof(int) * 4);
@@ -456,6 +463,9 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
         (void)hipGetLastError();
         return st;
     }
+    // address of this device's scratch array for lbm_shear_amplitude_noalloc (once per device);
+    // a failure here is reported by that entry point, not by the creation
+    (void)noalloc_setup(s->device);
     *out = s;
     return LBM_OK;
 }
@@ -491,8 +501,6 @@ lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double r
     if (st != LBM_OK) return st;
     if (!isfinite(u0) || !isfinite(rho_noise) || fabs(rho_noise) >= 1.0)
         return fail(LBM_EINVAL, "u0 and rho_noise must be finite, |rho_noise| < 1");
-    st = ensure_tables(s, wave_axis);
-    if (st != LBM_OK) return st;
     WaveArgs a{};
     a.f = s->buf[0];
     a.nx = s->g.nx;
@@ -503,7 +511,7 @@ lbm_status lbm_set_shear_wave(lbm_sim *s, double u0, int32_t wave_axis, double r
     a.u0 = u0;
     a.rho_noise = rho_noise;
     a.seed = seed;
-    a.sin_tab = s->d_tab;
+    a.sin_tab = sin_table(s, wave_axis);
     HIP_TRY(s->ks->init_wave(a, s->stream));
     s->cur = 0;
     s->nstep = 0;
@@ -581,6 +589,23 @@ lbm_status lbm_shear_amplitude(lbm_sim *s, int32_t wave_axis, double *a_sin, dou
     const double scale = 2.0 / (double)s->ncell;
     if (a_sin) *a_sin = scale * r[0];
     if (a_cos) *a_cos = scale * r[1];
+    return LBM_OK;
+}
+
+lbm_status lbm_shear_amplitude_noalloc(lbm_sim *s, int32_t wave_axis, double *dev_out) {
+    if (!s || !dev_out) return fail(LBM_EINVAL, "NULL argument");
+    lbm_status st = check_axis(s, wave_axis);
+    if (st != LBM_OK) return st;
+    if (6u * s->diag_blocks > kNoAllocFinal)
+        return fail(LBM_EINVAL, "reduction of %u workgroups exceeds the scratch of %u workgroups", s->diag_blocks,
+                    kNoAllocFinal / 6u);
+    double *scr = nullptr;
+    const hipError_t e = noalloc_scratch(s->device, &scr);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "device scratch unavailable on device %d: %s", s->device, hipGetErrorString(e));
+    const DiagArgs a = diag_args(s, wave_axis, scr);
+    HIP_TRY(s->ks->diag(a, s->diag_blocks, s->stream));
+    HIP_TRY(diag_final(scr, s->diag_blocks, 6, scr + kNoAllocFinal, s->stream));
+    HIP_TRY(noalloc_scale2(scr + kNoAllocFinal, 2.0 / (double)s->ncell, dev_out, s->stream));
     return LBM_OK;
 }
 

@@ -72,6 +72,7 @@ SIGNATURES = {
     "lbm_moments": (ctypes.c_int, [_SIM, _D, _D]),
     "lbm_shear_amplitude": (ctypes.c_int, [_SIM, ctypes.c_int32, _D, _D]),
     "lbm_totals": (ctypes.c_int, [_SIM, _D, _D]),
+    "lbm_shear_amplitude_noalloc": (ctypes.c_int, [_SIM, ctypes.c_int32, ctypes.c_void_p]),
     "lbm_get_populations": (ctypes.c_int, [_SIM, _D]),
     "lbm_set_populations": (ctypes.c_int, [_SIM, _D]),
     "lbm_get_cells": (ctypes.c_int, [_SIM, _I64, ctypes.c_int64, _D]),
