@@ -367,6 +367,13 @@ lbm_status lbm_rdvm_state(lbm_rdvm *r, int32_t index, double *g);
 lbm_status lbm_rdvm_info(const lbm_rdvm *r, int32_t index, double *dt, double *omega, int64_t *step);
 void lbm_rdvm_free(lbm_rdvm *r);   /* NULL-safe */
 
+/* Measurement aid: copy `bytes` of device memory from src to dst (asynchronous, on hip_stream;
+ * NULL = null stream) with a grid-stride loop of `blocks` workgroups of 256 threads, 16-byte
+ * vector loads and non-temporal 16-byte stores.  Its bandwidth, 2 * bytes / time, is the
+ * practical ceiling for a kernel that reads and writes each byte once.  LBM_EINVAL for NULL
+ * pointers, sizes or addresses that are not multiples of 16, blocks < 1, or overlap. */
+lbm_status lbm_device_copy(void *dst, const void *src, int64_t bytes, int32_t blocks, void *hip_stream);
+
 /* Thread-local text of the last error (empty string if none). */
 const char *lbm_last_error(void);
 

@@ -34,4 +34,18 @@ hipError_t fill_zero(int *p, uint32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Grid-stride copy of n 16-byte words: aligned vector loads, non-temporal vector stores.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(src[i], dst + i);
+}
+
+hipError_t copy16(const void *src, void *dst, uint64_t words, uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(256), 0, s, static_cast<const u32x4 *>(src),
+                       static_cast<u32x4 *>(dst), words);
+    return hipGetLastError();
+}
+
 }  // namespace lbm

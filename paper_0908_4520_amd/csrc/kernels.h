@@ -117,8 +117,9 @@ struct KernelSet {
     StepFn shift_rows4;    // on-lattice shift, 4 cells per thread, vector loads and stores, non-temporal
                            // loads (FP32 storages, |c_x| <= 4, nx a multiple of 256; else null)
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
-    StepBW32 bw2_f32;      // Beam-Warming advection (2-D sets), FP32 collision
-    StepBW64 bw2_f64;      // Beam-Warming advection (2-D sets), FP64 collision
+    StepBW32 bw2_f32[3];   // Beam-Warming advection (2-D sets), FP32 collision: plain stores,
+                           // non-temporal stores, non-temporal stores with alternating strip walks
+    StepBW64 bw2_f64[3];   // the same with the FP64 collision
     // The same with the body force (row tiles: 256 threads with plain stores, 512 threads with
     // non-temporal stores)
     StepFn shift_rows_forced[2];
@@ -149,6 +150,9 @@ void register_D2Q25_CK();
 
 // Zero n ints with a kernel (kept out of hipMemsetAsync so the step path can be captured).
 hipError_t fill_zero(int *p, uint32_t n, hipStream_t s);
+
+// Grid-stride copy of `words` 16-byte words with `blocks` workgroups of 256 threads.
+hipError_t copy16(const void *src, void *dst, uint64_t words, uint32_t blocks, hipStream_t s);
 
 // Fixed-order final reduction of per-block partial sums: out[k] = sum_b partials[b][k],
 // k < width <= 8 (width 6 for DiagFn partials, 2 for the stress sums of the forced steps).

@@ -294,14 +294,20 @@ __global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
 
 // ---------------------------------------------------------------- Beam-Warming, 2-D
 // Thread = one column x walking a strip of `tile` rows; a wave owns 64 consecutive
-// (aligned) columns.  For each population it keeps the x-advected values of the two
-// upwind rows in registers (sliding window over y).  The x-neighbours x - s, x - 2s come
-// from neighbouring lanes by DPP shifts; the two columns left (right) of the wave come from
-// one extra load per population-row that touches a single cache line and enter the shift as
-// the value of the vacated lane.  So every population-row costs one aligned load, one
-// one-line halo load and three lane shifts; stores are whole aligned wave segments.
+// (aligned) columns.  For each population it keeps the x-advected values of two rows of its
+// three-row upwind stencil in registers (sliding window over y) and loads one new row per
+// step.  The x-neighbours x - s, x - 2s come from neighbouring lanes by DPP shifts; the two
+// columns left (right) of the wave come from one extra load per population-row that touches a
+// single cache line and enter the shift as the value of the vacated lane.  So every
+// population-row costs one aligned load, one one-line halo load and three lane shifts; stores
+// are whole aligned wave segments (non-temporal with NTS: the output is not read again in this
+// step).  With ALT the odd strips walk up (decreasing y) and the even ones down, so two strips
+// start and end at their shared edges at the same time and the rows there, which both read,
+// meet in the L2 instead of being fetched twice; the window slides either way (for a population
+// whose stencil points along the walk it holds rows y, y + d and loads y + 2d, otherwise it
+// holds y - 2d, y - d and loads y).
 // With F the collision adds the body force (force axis y) and the stress sums are stored.
-template <class L, int N, int S, bool SR, class T, bool F>
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT>
 __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
     using C = Codec<S>;
@@ -344,58 +350,71 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
         }
         return f0 - cf.alpha[0][i] * (f0 - f1) + cf.beta[0][i] * (f1 - f2);
     };
-    T A[L::Q], B[L::Q];
-    {
-        const size_t rm2 = row_of(y0 - 2), rm1 = row_of(y0 - 1), r0 = row_of(y0), rp1 = row_of(y0 + 1);
-        static_for<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (L::xi[i][1] > 0.0) {
-                A[i] = xadv(I, rm2);
-                B[i] = xadv(I, rm1);
-            } else {
-                A[i] = xadv(I, r0);
-                B[i] = xadv(I, rp1);
-            }
-        });
-    }
     const T om = (T)a.omega;
     double ss = 0.0, sc = 0.0;
-    for (int y = y0; y < y1; ++y) {
-        T v[L::Q];
-        const size_t r0 = row_of(y), rp2 = row_of(y + 2);
+    // walk the strip in direction D (+1: increasing y from y0, -1: decreasing y from y1 - 1)
+    auto walk = [&](auto Dir) {
+        constexpr int D = decltype(Dir)::value;
+        const int ys = D > 0 ? y0 : y1 - 1;
+        T A[L::Q], B[L::Q];
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            if constexpr (L::xi[i][1] > 0.0) {      // upwind rows y-2 (A), y-1 (B), y (new)
-                const T Cn = xadv(I, r0);
-                v[i] = Cn - cf.alpha[1][i] * (Cn - B[i]) + cf.beta[1][i] * (B[i] - A[i]);
-                A[i] = B[i];
-                B[i] = Cn;
-            } else {                                 // upwind rows y (A), y+1 (B), y+2 (new)
-                const T Cn = xadv(I, rp2);
-                v[i] = A[i] - cf.alpha[1][i] * (A[i] - B[i]) + cf.beta[1][i] * (B[i] - Cn);
-                A[i] = B[i];
-                B[i] = Cn;
+            constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);   // stencil rows y, y+D, y+2D
+            if constexpr (along) {
+                A[i] = xadv(I, row_of(ys));
+                B[i] = xadv(I, row_of(ys + D));
+            } else {                                                  // rows y-2D, y-D, y
+                A[i] = xadv(I, row_of(ys - 2 * D));
+                B[i] = xadv(I, row_of(ys - D));
             }
         });
-        if constexpr (F) {
-            T sig[2];
-            collide_impl<L, N, S, T, true>(v, om, (T)(a.force_g * a.force_cos[y]), sig);
-            if (owner) {
-                ss += (double)sig[0] * a.force_sin[y];
-                sc += (double)sig[0] * a.force_cos[y];
-            }
-        } else {
-            collide<L, N, S, T>(v, om);
-        }
-        if (owner) {
-            const size_t o = r0 + (size_t)xo;
-            const uint32_t h = SR ? mix32((uint32_t)(y * nx + xo) ^ a.sr_key) : 0u;
+        for (int k = 0; k < y1 - y0; ++k) {
+            const int y = ys + D * k;
+            T v[L::Q];
+            const size_t r0 = row_of(y), r2 = row_of(y + 2 * D);
             static_for<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+                constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
+                if constexpr (along) {             // A = row y, B = row y+D, new row y+2D
+                    const T Cn = xadv(I, r2);
+                    v[i] = A[i] - cf.alpha[1][i] * (A[i] - B[i]) + cf.beta[1][i] * (B[i] - Cn);
+                    A[i] = B[i];
+                    B[i] = Cn;
+                } else {                           // A = row y-2D, B = row y-D, new row y
+                    const T Cn = xadv(I, r0);
+                    v[i] = Cn - cf.alpha[1][i] * (Cn - B[i]) + cf.beta[1][i] * (B[i] - A[i]);
+                    A[i] = B[i];
+                    B[i] = Cn;
+                }
             });
+            if constexpr (F) {
+                T sig[2];
+                collide_impl<L, N, S, T, true>(v, om, (T)(a.force_g * a.force_cos[y]), sig);
+                if (owner) {
+                    ss += (double)sig[0] * a.force_sin[y];
+                    sc += (double)sig[0] * a.force_cos[y];
+                }
+            } else {
+                collide<L, N, S, T>(v, om);
+            }
+            if (owner) {
+                const size_t o = r0 + (size_t)xo;
+                const uint32_t h = SR ? mix32((uint32_t)(y * nx + xo) ^ a.sr_key) : 0u;
+                static_for<L::Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+                    if constexpr (NTS)
+                        __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
+                    else
+                        fout[(size_t)i * ps + o] = r;
+                });
+            }
         }
-    }
+    };
+    if (ALT && (strip & 1u))
+        walk(std::integral_constant<int, -1>{});
+    else
+        walk(std::integral_constant<int, 1>{});
     if constexpr (F)
         if (a.stress) store_stress<kBlock>(a.stress, ss, sc);
 }
@@ -586,9 +605,9 @@ hipError_t launch_shift_cells(const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_shift_cells<L, N, S, SR, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
-template <class L, int N, int S, bool SR, class T, bool F>
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT>
 hipError_t launch_bw2(const StepArgs &a, const BWCoef<T> &cf, hipStream_t s) {
-    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
+    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F, NTS, ALT>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
     return hipGetLastError();
 }
 template <class L, int N, int S>
@@ -661,11 +680,15 @@ KernelSet make_set() {
         k.shift_cells_forced = &launch_shift_cells<L, N, S, SR, true>;
     } else if constexpr (L::D == 2) {
         if constexpr (S == ST_FP64) {
-            k.bw2_f64 = &launch_bw2<L, N, S, SR, double, false>;
-            k.bw2_f64_forced = &launch_bw2<L, N, S, SR, double, true>;
+            k.bw2_f64[0] = &launch_bw2<L, N, S, SR, double, false, false, false>;
+            k.bw2_f64[1] = &launch_bw2<L, N, S, SR, double, false, true, false>;
+            k.bw2_f64[2] = &launch_bw2<L, N, S, SR, double, false, true, true>;
+            k.bw2_f64_forced = &launch_bw2<L, N, S, SR, double, true, false, false>;
         } else {
-            k.bw2_f32 = &launch_bw2<L, N, S, SR, float, false>;
-            k.bw2_f32_forced = &launch_bw2<L, N, S, SR, float, true>;
+            k.bw2_f32[0] = &launch_bw2<L, N, S, SR, float, false, false, false>;
+            k.bw2_f32[1] = &launch_bw2<L, N, S, SR, float, false, true, false>;
+            k.bw2_f32[2] = &launch_bw2<L, N, S, SR, float, false, true, true>;
+            k.bw2_f32_forced = &launch_bw2<L, N, S, SR, float, true, false, false>;
         }
     }
     k.init_wave = &launch_init_wave<L, N, S>;

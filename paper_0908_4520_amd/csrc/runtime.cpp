@@ -115,7 +115,15 @@ const ShiftTile kShiftTiles[] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256,
                                  {2, 512, 2}, {2, 512, 1}, {1, 256, 4}, {1, 256, 8}, {3, 256, 1},
                                  {3, 256, 2}};
 constexpr int kPlainShiftTiles = 9;   // without the vector tiles
-const int kBWTiles[] = {16, 32, 8, 4, 64};
+// Beam-Warming: rows per strip and variant (0: plain stores, 1: non-temporal stores, 2: non-temporal
+// stores and alternating walk directions of neighbouring strips).  The forced kernel exists for
+// variant 0 only: the first kForcedBWTiles tiles.
+struct BWTile {
+    int rows, variant;
+};
+const BWTile kBWTiles[] = {{16, 0}, {32, 0}, {8, 0}, {4, 0},  {64, 0}, {16, 1}, {32, 1},
+                           {8, 1},  {16, 2}, {32, 2}, {8, 2}, {4, 2},  {64, 2}};
+constexpr int kForcedBWTiles = 5;
 
 }  // namespace
 
@@ -178,7 +186,7 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     a.sr_key = (uint32_t)splitmix64(s->o.sr_seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(s->nstep + 1)));
     const uint32_t nx = (uint32_t)s->g.nx;
     if (s->move == LBM_MOVE_BW2) {
-        const uint32_t H = (uint32_t)kBWTiles[tile_index];
+        const uint32_t H = (uint32_t)kBWTiles[tile_index].rows;
         a.tile = H;
         a.per_row = (nx + kBlock - 1) / kBlock;   // blocks of 4 waves x 64 columns
         a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
@@ -225,8 +233,10 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
         if (!s->rows_ok) return k->shift_cells_forced(a, s->stream);
         return k->shift_rows_forced[kShiftTiles[tile_index].variant == 2 ? 1 : 0](a, s->stream);
     }
-    if (s->move == LBM_MOVE_BW2)
-        return s->o.storage == LBM_FP64 ? k->bw2_f64(a, s->bwd, s->stream) : k->bw2_f32(a, s->bwf, s->stream);
+    if (s->move == LBM_MOVE_BW2) {
+        const int v = kBWTiles[tile_index].variant;
+        return s->o.storage == LBM_FP64 ? k->bw2_f64[v](a, s->bwd, s->stream) : k->bw2_f32[v](a, s->bwf, s->stream);
+    }
     if (!s->rows_ok) return k->shift_cells(a, s->stream);
     const int v = kShiftTiles[tile_index].variant;
     return v == 3 ? k->shift_rows4(a, s->stream) : k->shift_rows[v](a, s->stream);
@@ -239,7 +249,7 @@ constexpr int kForcedShiftTiles = 7;
 bool vector_tiles_ok(const lbm_sim *s) { return s->ks->shift_rows4 != nullptr && s->g.nx % 256 == 0; }
 
 int tile_count(const lbm_sim *s) {
-    if (s->move == LBM_MOVE_BW2) return (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
+    if (s->move == LBM_MOVE_BW2) return s->forced ? kForcedBWTiles : (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
     if (s->rows_ok) {
         if (s->forced) return kForcedShiftTiles;
         return vector_tiles_ok(s) ? (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]) : kPlainShiftTiles;
@@ -725,6 +735,18 @@ lbm_status lbm_load_state(lbm_sim *s, const void *host, int64_t bytes) {
     return LBM_OK;
 }
 
+lbm_status lbm_device_copy(void *dst, const void *src, int64_t bytes, int32_t blocks, void *hip_stream) {
+    if (!dst || !src || bytes < 0) return fail(LBM_EINVAL, "NULL pointer or negative size");
+    if ((((uintptr_t)dst | (uintptr_t)src | (uintptr_t)bytes) & 15u) != 0)
+        return fail(LBM_EINVAL, "pointers and size must be multiples of 16 bytes");
+    if (blocks < 1) return fail(LBM_EINVAL, "blocks must be >= 1");
+    const uintptr_t d = (uintptr_t)dst, sp = (uintptr_t)src;
+    if (bytes > 0 && (d < sp ? sp - d : d - sp) < (uint64_t)bytes) return fail(LBM_EINVAL, "buffers overlap");
+    if (bytes == 0) return LBM_OK;
+    HIP_TRY(copy16(src, dst, (uint64_t)bytes / 16u, (uint32_t)blocks, (hipStream_t)hip_stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_fit_decay(const double *amp, const int64_t *steps, int64_t count, int64_t n_first, int64_t n_last,
                          double *gamma) {
     if (!amp || !steps || !gamma || count < 0) return fail(LBM_EINVAL, "NULL argument or negative count");
@@ -869,7 +891,8 @@ lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads,
     if (cells_per_thread) *cells_per_thread = (int32_t)a.tile * vw;
     if (vector_width) *vector_width = vw;
     if (blocks) *blocks = (int64_t)a.nblocks;
-    if (nontemporal) *nontemporal = rows && kShiftTiles[tile].variant != 0;
+    if (nontemporal)
+        *nontemporal = rows ? kShiftTiles[tile].variant != 0 : (s->move == LBM_MOVE_BW2 && kBWTiles[tile].variant != 0);
     return LBM_OK;
 }
 

@@ -108,6 +108,8 @@ SIGNATURES = {
     "lbm_rdvm_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D]),
     "lbm_rdvm_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D, _D, _I64]),
     "lbm_rdvm_free": (None, [ctypes.c_void_p]),
+    "lbm_device_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -185,6 +187,12 @@ def lbm_fit_oscillation(amp, steps, dt: float, frequency: float, n_first: int, n
     _check(_lib.lbm_fit_oscillation(_dp(a), st.ctypes.data_as(_I64), len(a), dt, frequency, n_first, n_last,
                                     ctypes.byref(re), ctypes.byref(im)))
     return complex(re.value, im.value)
+
+
+def lbm_device_copy(dst: int, src: int, nbytes: int, blocks: int = 1024, stream=None):
+    """Grid-stride 16-byte copy of nbytes from device address src to dst (asynchronous)."""
+    _check(_lib.lbm_device_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, blocks,
+                                None if stream is None else ctypes.c_void_p(stream)))
 
 
 def lbm_fit_decay(amp, steps, n_first: int, n_last: int) -> float:

@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import need_gpu, perm, say
+from gpu_helpers import need_gpu, oracle_columns, perm, say
 from oracle import bgk as ob
 from oracle import lattices as OL
 from oracle import linmode
@@ -148,12 +148,37 @@ def _linear_series(lat, tau, ny, steps, every):
     return np.array(out)
 
 
+A_FLOOR = 1e-3     # fit window ends where the oracle amplitude falls below A_FLOOR * A0
+
+
+def decay_window(ref, ns, n_first):
+    """Reading of the decay-rate definition (least-squares slope of -ln A_s over n >= ceil(10 tau)):
+    the window runs from ceil(10 tau) to the last record at which the oracle's amplitude is still
+    at least 1e-3 A0.  Below that the amplitude is within a factor 100 of the FP32 amplitude bar
+    (1e-5 A0) and of the noise floor FP32 storage leaves after thousands of steps, so the tail
+    of a fast-decaying instance (some fall to 1e-11 A0 within the 5000 steps) would fit the
+    rounding noise, not the decay.  A rate is defined where, over that window, the oracle's
+    amplitude stays positive and decreases at every record (no oscillation or sign change),
+    over at least 10 records, and falls by at least 10%; returns (n_first, n_last) or None.
+    Elsewhere the series themselves are compared."""
+    sel = (ns >= n_first) & (ref >= A_FLOOR * A0)
+    idx = np.nonzero(sel)[0]
+    if len(idx) < 10 or not np.all(np.diff(idx) == 1):
+        return None
+    w = ref[idx]
+    if np.all(w > 0) and np.all(np.diff(w) < 0) and w[-1] <= 0.9 * w[0]:
+        return int(ns[idx[0]]), int(ns[idx[-1]])
+    return None
+
+
 def test_kn_sweep_256_instances_5000_steps():
     """256 instances (seed 0: ny in [32, 1024], D2Q9 / D2Q16-GH / D2Q36-GH / D2Q37, Kn
-    log-uniform in [0.01, 10], nx = 4), FP32 deviations, 5000 steps, amplitude every 50 steps.
-    Every series against the linear single-mode prediction (O(u0^2) and FP32 tolerance
-    2e-5 A0); a sample of 12 instances against the oracle itself (1 x ny column, exact for
-    x-uniform data); decay rates, where the amplitude decays monotonically, within 1e-4."""
+    log-uniform in [0.01, 10], nx = 4), FP32 deviations, 5000 steps, amplitude every 50 steps,
+    in the autotuned persistent form.  Every instance against the FP64 oracle run on its
+    1 x ny column (exact for the x-uniform wave): the whole amplitude series within 1e-5 A0,
+    the final populations of all four columns within 1e-5 relative, and, wherever a decay rate
+    is defined (decay_window), the decay rate within 1e-4 relative.  Every series also
+    against the linear single-mode prediction (O(u0^2) model error plus FP32: 2e-5 A0)."""
     from paper_0908_4520_amd import workloads
     lbm = need_gpu()
     w = workloads.batch_instances(0, 256)
@@ -163,42 +188,38 @@ def test_kn_sweep_256_instances_5000_steps():
         form, blk, ms = b.autotune(20)
         b.reset()
         amp = b.run(steps, every)
-    say(f"Kn sweep: form {form} block {blk}, {ms:.4f} ms/step autotune")
+        pops = [b.populations(i) for i in range(len(inst))]
+    say(f"Kn sweep: form {form} block {blk}, {ms:.4f} ms/step autotune; running the oracle on 256 columns ...")
+    ref = oracle_columns([(lat, N, tau, ny, A0, steps, every) for lat, N, tau, (nx, ny), _ in inst])
     ns = np.arange(0, steps + 1, every)
-    errs = []
-    gam_err = []
+    errs, lin_errs, f_errs, gam = [], [], [], []
     for i, (lat, N, tau, (nx, ny), _) in enumerate(inst):
-        lin = _linear_series(lat, tau, ny, steps, every)
-        errs.append(float(np.max(np.abs(amp[i] - lin))) / A0)
-        n_first = math.ceil(10 * tau)
-        sel = (ns >= n_first)
-        if sel.sum() >= 10 and np.all(lin[sel] > 0.02 * A0) and np.all(np.diff(lin[sel]) < 0):
-            g_l = ob.decay_rate(lin, ns, n_first, steps)
-            g_b = lbm.lbm_fit_decay(amp[i], ns, n_first, steps)
-            gam_err.append((abs(g_b - g_l) / g_l, i))
-    errs = np.array(errs)
-    worst = np.argsort(errs)[::-1][:8]
-    say(f"Kn sweep: worst |A - A_linear|/A0 {errs.max():.2e}; decay-rate errors over {len(gam_err)} instances: "
-        f"max {max(gam_err)[0]:.2e} (instance {max(gam_err)[1]}) median {np.median([g for g, _ in gam_err]):.2e}")
-    for i in worst:
+        a_ref, f_ref = ref[i]
+        errs.append(float(np.max(np.abs(amp[i] - a_ref))) / A0)
+        lin_errs.append(float(np.max(np.abs(amp[i] - _linear_series(lat, tau, ny, steps, every)))) / A0)
+        fr = f_ref[perm(lat)]                                      # (Q, ny)
+        f = pops[i].reshape(-1, ny, nx)
+        f_errs.append(max(float(np.max(np.abs(f[:, :, x] - fr) / np.abs(fr))) for x in range(nx)))
+        win = decay_window(a_ref, ns, math.ceil(10 * tau))
+        if win is not None:
+            g_o = ob.decay_rate(a_ref, ns, *win)
+            g_b = lbm.lbm_fit_decay(amp[i], ns, *win)
+            gam.append((abs(g_b - g_o) / g_o, i))
+    errs, lin_errs, f_errs = np.array(errs), np.array(lin_errs), np.array(f_errs)
+    g_worst = max(gam) if gam else (0.0, -1)
+    say(f"Kn sweep vs the FP64 oracle, all 256 instances: max |dA|/A0 {errs.max():.2e} (instance {errs.argmax()}), "
+        f"median {np.median(errs):.2e}; populations max {f_errs.max():.2e}; vs linear theory max {lin_errs.max():.2e}")
+    say(f"Kn sweep decay rates over the {len(gam)} instances where defined: max rel err {g_worst[0]:.2e} "
+        f"(instance {g_worst[1]}), median {np.median([g for g, _ in gam]) if gam else 0.0:.2e}")
+    for i in np.argsort(errs)[::-1][:6]:
         lat, N, tau, (nx, ny), _ = inst[i]
-        say(f"  instance {i} {lat} ny={ny} tau={tau:.5g}: |A - A_lin|/A0 {errs[i]:.2e}")
-    # oracle columns: the worst against the prediction, the largest of each set, a few more
-    sample = set(int(i) for i in worst[:4]) | {max(gam_err)[1]}
-    for lat in workloads.BATCH_SETS:
-        idx = [i for i in range(256) if w[i][0] == lat]
-        sample.add(max(idx, key=lambda i: w[i][3]))
-    sample |= {3, 77, 150, 201, 255}
-    worst_oracle = 0.0
-    for i in sorted(sample):
-        lat, N, tau, (nx, ny), _ = inst[i]
-        ref, _ = _oracle_series(lat, N, tau, 1, ny, steps, every)
-        err = float(np.max(np.abs(amp[i] - ref))) / A0
-        lin_err = float(np.max(np.abs(_linear_series(lat, tau, ny, steps, every) - ref))) / A0
-        worst_oracle = max(worst_oracle, err)
-        say(f"Kn sweep instance {i} {lat} ny={ny} tau={tau:.5g}: |dA|/A0 vs oracle {err:.2e} (oracle vs linear {lin_err:.2e})")
-    assert worst_oracle <= 1e-5
-    assert max(gam_err)[0] <= 1e-4          # the decay-rate accuracy the FP32 batch is held to
+        say(f"  instance {i} {lat} N={N} ny={ny} tau={tau:.5g}: |dA|/A0 {errs[i]:.2e}, pops {f_errs[i]:.2e}, "
+            f"vs linear {lin_errs[i]:.2e}")
+    assert len(gam) >= 32
+    assert np.all(errs <= 1e-5)
+    assert np.all(f_errs <= 1e-5)
+    assert np.all(lin_errs <= 2e-5)
+    assert g_worst[0] <= 1e-4
 
 
 @pytest.mark.parametrize("form", [1, 2])

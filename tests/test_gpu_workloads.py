@@ -17,7 +17,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import need_gpu, perm, say
+from gpu_helpers import need_gpu, perm, rel_err, say
 from oracle import bgk as ob
 
 pytestmark = pytest.mark.gpu
@@ -124,12 +124,19 @@ def test_dvm_2048sq_sampled_cells_with_noise():
 
 # Decay-rate error of the reduced-precision storages (512^3 D3Q39, N = 4, Kn = 0.05,
 # 200 steps) against the FP64 oracle: required <= 1e-4 for FP32 deviations and for both
-# 16-bit formats with stochastic rounding.  With round-to-nearest the 16-bit formats cannot
-# meet it and are only reported: the data is uniform across x and y, so every column rounds
-# alike (no averaging), and a per-step change of a stored deviation that is smaller than
-# half its last place is rounded away every step (the slow decay stagnates).
+# 16-bit formats with stochastic rounding.  FP32 deviations are also held to the FP32 bar on
+# the amplitude series (1e-5 A0) and on the populations of full-size columns.  With
+# round-to-nearest the 16-bit formats cannot meet the decay-rate bar: the data is uniform
+# across x and y, so every column rounds alike (no averaging), and a per-step change of a
+# stored deviation that is smaller than half its last place is rounded away, identically
+# every step; the resulting bias (slower decay in BF16, faster in FP16 on this workload) is
+# far above 1e-4.  For them the test asserts exactly that expectation (the error exceeds the
+# bar that stochastic rounding meets) and reports the size.
 STORAGES = [("fp32_dev", False, 1e-4), ("fp16_dev", True, 1e-4), ("bf16_dev", True, 1e-4),
             ("fp16_dev", False, None), ("bf16_dev", False, None)]
+UNIT_ROUNDOFF = {"fp16_dev": 2.0**-11, "bf16_dev": 2.0**-8}
+# full-size columns checked against the oracle column: (x, y) of each, all 512 z
+COLUMNS = [(0, 0), (511, 511), (17, 300), (256, 3)]
 
 
 @pytest.fixture(scope="module")
@@ -141,27 +148,39 @@ def d3q39_column_oracle():
     a_ref, ns = _series_oracle(ref, 2, 200, 5)
     n_first = math.ceil(10 * tau)
     g_ref = ob.decay_rate(a_ref, ns, n_first, 200)
-    return tau, a_ref, ns, n_first, g_ref
+    return tau, a_ref, ns, n_first, g_ref, ref.f[perm("D3Q39")].copy()
 
 
 @pytest.mark.parametrize("storage,sr,tol", STORAGES)
 def test_d3q39_512cubed_decay_rate(d3q39_column_oracle, storage, sr, tol):
+    from gpu_helpers import dev_err, lowp_bound
+    from oracle import lattices as OL
     lbm = need_gpu()
-    tau, a_ref, ns, n_first, g_ref = d3q39_column_oracle
+    tau, a_ref, ns, n_first, g_ref, f_col = d3q39_column_oracle
+    cells = np.array([x + 512 * (y + 512 * z) for x, y in COLUMNS for z in range(512)], dtype=np.int64)
     with lbm.Sim("D3Q39", 4, tau, (512, 512, 512), storage=storage, stochastic_round=sr, sr_seed=2024) as s:
         s.set_shear_wave(A0, 2)
         s.autotune(3)                       # the benchmark's launch configuration
         s.set_shear_wave(A0, 2)
         a_gpu, _ = _series_gpu(s, 2, 200, 5)
+        f = s.get_cells(cells).reshape(39, len(COLUMNS), 512)
     g = lbm.lbm_fit_decay(a_gpu, ns, n_first, 200)
     rel = abs(g - g_ref) / g_ref
     amp_err = float(np.max(np.abs(a_gpu - a_ref))) / A0
+    w = OL.get("D3Q39").w[perm("D3Q39")]
+    col_rel = max(rel_err(f[:, k, :], f_col) for k in range(len(COLUMNS)))
+    col_dev = max(dev_err(f[:, k, :], f_col, w) for k in range(len(COLUMNS)))
     say(f"D3Q39 512^3 {storage}{' SR' if sr else ' RNE'}: gamma {g:.8e} oracle {g_ref:.8e} rel err {rel:.2e}; "
-        f"max |dA|/A0 {amp_err:.2e}")
-    if tol is not None:
+        f"max |dA|/A0 {amp_err:.2e}; columns rel {col_rel:.2e}, on the deviation scale {col_dev:.2e}")
+    if storage == "fp32_dev":
+        assert rel <= tol and amp_err <= 1e-5
+        assert col_rel <= 1e-5 and col_dev <= 1e-5
+    elif sr:
         assert rel <= tol
+        bound = lowp_bound(f_col, "D3Q39", UNIT_ROUNDOFF[storage], 200, tau)
+        assert all(np.all(np.abs(f[:, k, :] - f_col) <= bound) for k in range(len(COLUMNS)))
     else:
-        assert rel <= 1.0   # reported only
+        assert rel > 1e-4                   # round-to-nearest: biased, as expected
 
 
 @pytest.mark.parametrize("lattice,N", [("D2Q16-CK", 3), ("D2Q17", 3), ("D2Q21", 3), ("D2Q25-CK", 4)])
