@@ -261,7 +261,7 @@ lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, i
  * form below), replayed from a captured HIP graph, and records each instance's sine amplitude of u_x (as lbm_shear_amplitude,
  * wave along y) every record_every steps.  Supported: 2-D sets D2Q9, D2Q37 (exact shift),
  * D2Q16_GH, D2Q36_GH (Beam-Warming advection at o->cfl); eq_order 1..4; storage
- * LBM_FP32_DEV or LBM_FP64; wave_axis 1; nz = 1. */
+ * LBM_FP32_DEV or LBM_FP64; wave_axis 1; nz = 1; at most 2^26 cells per instance. */
 typedef struct {
     lbm_lattice lat;
     int32_t eq_order;

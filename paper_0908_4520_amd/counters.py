@@ -10,8 +10,8 @@ non-temporal stores), so one shape is one tile choice of one configuration.
   python -m paper_0908_4520_amd.counters traffic FETCH_DIR WRITE_DIR --calib-bytes B
           [--kernel REGEX --alg-read-bytes R --tag TAG --json profiles/traffic.json]
       HBM bytes per launch from two counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE;
-      KiB per dispatch).  Each counter is scaled by what it reads for the device copy
-      (__amd_rocclr_copyBuffer) of B bytes in the same run.  With --json, the entry TAG of that
+      KiB per dispatch).  Each counter is scaled by what it reads for the library's device copy
+      (lbm_device_copy: kernel lbm::k_copy16) of B bytes in the same run.  With --json, the entry TAG of that
       file is replaced by the shapes of the kernels matching REGEX, stamped with the digest of
       the kernel sources.
 """
@@ -28,7 +28,7 @@ from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("bgk_device.h", "kernels_impl.h", "kernels.h", "lattices.inc")
-COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_KERNEL = "lbm::k_copy16"     # name prefix of the calibration copy kernel (lbm_device_copy)
 
 
 def kernel_source_digest() -> str:
@@ -92,7 +92,7 @@ def calibration(fetch, write, nbytes: int):
     is the i-th of that shape in the write run."""
     f_vals, w_vals = [], []
     for k, ws in write.items():
-        if k[0] != COPY_KERNEL or len(fetch.get(k, [])) != len(ws):
+        if not k[0].startswith(COPY_KERNEL) or len(fetch.get(k, [])) != len(ws):
             continue
         for f, w in zip(fetch[k], ws):
             if abs(w * 1024 - nbytes) <= 0.02 * nbytes:
@@ -135,7 +135,7 @@ def cmd_traffic(args):
     shapes = {}
     for key in sorted(set(fetch) & set(write), key=lambda k: (k[0], k[1], k[2])):
         name, wg, nb = key
-        if name.startswith("__amd") or "lbm::" not in name:
+        if name.startswith("__amd") or "lbm::" not in name or name.startswith(COPY_KERNEL):
             continue
         f = sum(fetch[key]) / len(fetch[key])
         w = sum(write[key]) / len(write[key])

@@ -182,20 +182,7 @@ struct Moments {
 template <class L, int S, class T>
 __device__ __forceinline__ Moments<T> project(const T (&v)[L::Q]) {
     // per velocity pair (xi, -xi): the sum feeds the density, the difference the momentum.
-    // Scaled (FP16) storage keeps the per-population sums: the pair form needs more registers
-    // than its row kernel's occupancy target leaves.
     Moments<T> m{T(0), T(0), T(0), T(0)};
-    if constexpr (Codec<S>::scaled) {
-        static_for<L::Q>([&](auto I) {
-            constexpr int a = decltype(I)::value;
-            const T g = T(moment_factor<L, S, a>()) * v[a];
-            m.d += g;
-            if constexpr (L::xi[a][0] != 0.0) m.jx += T(L::xi[a][0]) * g;
-            if constexpr (L::xi[a][1] != 0.0) m.jy += T(L::xi[a][1]) * g;
-            if constexpr (L::D == 3 && L::xi[a][2] != 0.0) m.jz += T(L::xi[a][2]) * g;
-        });
-        return m;
-    }
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
         constexpr int b = opposite<L>(a);
@@ -263,6 +250,45 @@ __device__ __forceinline__ void collide_impl(T (&v)[L::Q], T omega, T Gx, T (&si
     const T rG = rho * Gx, rGu = rho * Gx * ux, b0 = T(1) - T(0.5) * q;
     const T kf = T(1) - T(0.5) * omega;
     T sxy = T(0), sxz = T(0);
+    if constexpr (Codec<S>::lowp && !FORCED) {
+        // 16-bit storages: the polynomial per velocity pair (xi, -xi), P(+-s) = E(s^2) +- s O(s^2).
+        // Its rounding differs from the per-population Horner form in the last bits of FP32, far
+        // below the storage's 8 or 11 bits (where FP32 storage needs the per-population form:
+        // the two roundings fl(E + sO), fl(E - sO) round E's low bits alike, so a pair's mass
+        // errors no longer cancel).
+        static_for<L::Q>([&](auto I) {
+            constexpr int a = decltype(I)::value;
+            constexpr int b = opposite<L>(a);
+            constexpr double ef = eq_factor<L, S, a>();
+            if constexpr (b == a) {
+                const T neq = (ef == 1.0) ? (C0 - v[a]) + D0 : (T(ef) * C0 - v[a]) + T(ef) * D0;
+                v[a] = v[a] + omega * neq;
+            } else if constexpr (b > a) {
+                T s = T(0);
+                if constexpr (L::xi[a][0] != 0.0) s += T(L::xi[a][0]) * ux;
+                if constexpr (L::xi[a][1] != 0.0) s += T(L::xi[a][1]) * uy;
+                if constexpr (L::D == 3 && L::xi[a][2] != 0.0) s += T(L::xi[a][2]) * uz;
+                const T s2 = s * s;
+                T E = C0, O = C1;
+                if constexpr (N == 2 || N == 3) E = C0 + s2 * C2;
+                if constexpr (N == 4) E = C0 + s2 * (C2 + s2 * C4);
+                if constexpr (N >= 3) O = C1 + s2 * C3;
+                const T sO = s * O, sD = s * D1;
+                const T pa = E + sO, pb = E - sO, ca = D0 + sD, cb = D0 - sD;
+                T na, nb;
+                if constexpr (ef == 1.0) {
+                    na = (pa - v[a]) + ca;
+                    nb = (pb - v[b]) + cb;
+                } else {
+                    na = (T(ef) * pa - v[a]) + T(ef) * ca;
+                    nb = (T(ef) * pb - v[b]) + T(ef) * cb;
+                }
+                v[a] = v[a] + omega * na;
+                v[b] = v[b] + omega * nb;
+            }
+        });
+        return;
+    }
     static_for<L::Q>([&](auto I) {
         constexpr int a = decltype(I)::value;
         T s = T(0);

@@ -15,14 +15,43 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
     return (nblocks & 7u) == 0u ? (bid & 7u) * (nblocks >> 3) + (bid >> 3) : bid;
 }
 
-// Per-population stochastic-rounding bits from one hash per cell.  Populations 2k and 2k + 1
-// share one hashed word, the odd one rotated by 16 bits: the conversions read a window of at
-// most 16 of the 32 bits (the 16 bits BF16 drops from FP32, the 13 FP16 drops), so the two
-// populations see disjoint bits of the word, and a cell needs ceil(Q / 2) hashes (each two
-// quarter-rate multiplies) instead of Q.
-__device__ __forceinline__ uint32_t pop_bits(uint32_t cell_hash, int a) {
-    const uint32_t w = mix32(cell_hash + 0x9e3779b9u * (uint32_t)((a >> 1) + 1));
-    return (a & 1) ? (w >> 16) | (w << 16) : w;
+// Stochastic-rounding bits.  A conversion reads a window of at most 16 of its 32 random bits
+// (the low 16 bits: the 16 bits BF16 drops from FP32, the 13 FP16 drops).  Each cell hashes its
+// index with the step's key twice (h1, h2: two multiply-xorshift finalisers, the only
+// quarter-rate work); population pair k takes the word w_k = rotl(h1, r1_k) ^ rotl(h2, r2_k),
+// population 2k its low half and 2k + 1 its high half (w_k rotated by 16).  The rotation pairs
+// below were chosen so that, for (h1, h2) uniform, the 16-bit windows of any two of the first 39
+// populations are jointly uniform (the 32 x 64 bit matrix mapping (h1, h2) to the two windows
+// has full rank over GF(2)): every population's rounding is unbiased and any two populations
+// of a cell round independently, at three full-rate operations per pair instead of one hash.
+// A CPU test re-derives the rank condition from this table.
+struct CellBits {
+    uint32_t h1, h2;
+};
+constexpr int kSrRot[20][2] = {{24, 22}, {26, 14}, {21, 1}, {17, 10}, {20, 6}, {13, 17}, {18, 7},
+                               {4, 30},  {30, 5},  {22, 4}, {26, 9},  {1, 18}, {27, 26}, {7, 2},
+                               {2, 24},  {21, 17}, {15, 2}, {19, 0},  {4, 6},  {2, 12}};
+__device__ __forceinline__ CellBits cell_bits(uint32_t cell, uint32_t key) {
+    return CellBits{mix32(cell ^ key), mix32((cell ^ key) + 0x9e3779b9u)};
+}
+template <int A>
+__device__ __forceinline__ uint32_t pop_bits(const CellBits &c) {
+    static_assert(A < 40, "rotation table covers 40 populations");
+    constexpr int k = A >> 1;
+    const uint32_t w = __builtin_rotateleft32(c.h1, kSrRot[k][0]) ^ __builtin_rotateleft32(c.h2, kSrRot[k][1]);
+    return (A & 1) ? __builtin_rotateleft32(w, 16) : w;
+}
+__device__ __forceinline__ uint32_t pop_bits_rt(const CellBits &c, int a) {   // runtime population index
+    const int k = a >> 1;
+    uint32_t r1 = 0, r2 = 0;
+#pragma unroll
+    for (int j = 0; j < 20; ++j)
+        if (j == k) {
+            r1 = (uint32_t)kSrRot[j][0];
+            r2 = (uint32_t)kSrRot[j][1];
+        }
+    const uint32_t w = __builtin_rotateleft32(c.h1, r1) ^ __builtin_rotateleft32(c.h2, r2);
+    return (a & 1) ? __builtin_rotateleft32(w, 16) : w;
 }
 
 __device__ __forceinline__ int wrap_once(int v, int n) {   // |v| < 2n
@@ -83,16 +112,8 @@ __device__ __forceinline__ double dpp_shl(double old, double v) {
 // with NTS, non-temporal: the output is not read again in this step, and streaming it past
 // the L2 leaves room for the cache lines that neighbouring chunks share through the x-shifts.
 // With F the collision adds the body force of the row and the stress sums are stored.
-// Occupancy hint (waves per SIMD) for the row kernel: the unforced FP16 path with stochastic
-// rounding otherwise settles at 95 registers (5 waves); it fits 80 (6 waves) without spilling.
-template <int S, bool SR, bool F>
-constexpr int row_waves_per_eu() {
-    return (S == ST_FP16_DEV && SR && !F) ? 6 : 1;
-}
-
 template <class L, int N, int S, bool SR, int BLOCK, bool NTS, bool F>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu<S, SR, F>())))
-void k_shift_rows(StepArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;
@@ -101,9 +122,14 @@ void k_shift_rows(StepArgs a) {
     const uint32_t xb = lb - row * a.per_row;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
-    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
-    raw *__restrict__ fout = static_cast<raw *>(a.fout);
-    const size_t ps = a.lay.pop, rs = a.lay.row;
+    // Addresses: a 64-bit scalar base per source row (one per distinct (c_y, c_z), shared by the
+    // populations moving along it) plus a 32-bit lane offset, population * (bytes between
+    // populations) + x-offset, which the load and store instructions add themselves.  A row of all
+    // Q populations is below 2^31 bytes (checked by the host), so the offset cannot wrap.
+    const char *__restrict__ fin = static_cast<const char *>(a.fin);
+    char *__restrict__ fout = static_cast<char *>(a.fout);
+    const uint32_t ps = (uint32_t)a.lay.pop * (uint32_t)sizeof(raw);
+    const size_t rs = (size_t)a.lay.row * sizeof(raw);
     const T om = (T)a.omega;
     const int jf = a.force_axis == 1 ? y : z;           // row index along the force axis
     T Gx = T(0);
@@ -112,7 +138,7 @@ void k_shift_rows(StepArgs a) {
     for (uint32_t k = 0; k < a.tile; ++k) {
         const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
         if (x >= nx) break;
-        T v[L::Q];
+        raw rv[L::Q];
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
@@ -124,8 +150,17 @@ void k_shift_rows(StepArgs a) {
             int xs = x - cx;
             if constexpr (cx > 0) xs += (xs < 0) ? nx : 0;
             if constexpr (cx < 0) xs -= (xs >= nx) ? nx : 0;
-            const raw *p = fin + (size_t)i * ps + (size_t)(ys + ny * zs) * rs;
-            v[i] = C::dec(p[xs]);
+            const char *rb = fin + (size_t)(ys + ny * zs) * rs;
+            const uint32_t off = (uint32_t)i * ps + (uint32_t)xs * (uint32_t)sizeof(raw);
+            rv[i] = *reinterpret_cast<const raw *>(rb + off);
+        });
+        // all Q loads are issued before any is used: left to itself the scheduler may, under
+        // register pressure, wait for each load before issuing the next
+        __builtin_amdgcn_sched_barrier(0);
+        T v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            v[i] = C::dec(rv[i]);
         });
         if constexpr (F) {
             T sig[2];
@@ -135,15 +170,18 @@ void k_shift_rows(StepArgs a) {
             collide<L, N, S, T>(v, om);
         }
         const uint32_t cell = row * (uint32_t)nx + (uint32_t)x;
-        const size_t o = (size_t)row * rs + (size_t)x;
-        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+        char *ob = fout + (size_t)row * rs;
+        const uint32_t xo = (uint32_t)x * (uint32_t)sizeof(raw);
+        CellBits hb{0u, 0u};
+        if constexpr (SR) hb = cell_bits(cell, a.sr_key);
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            const raw r = C::template enc<SR>(v[i], SR ? pop_bits<i>(hb) : 0u);
+            raw *dst = reinterpret_cast<raw *>(ob + ((uint32_t)i * ps + xo));
             if constexpr (NTS)
-                __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
+                __builtin_nontemporal_store(r, dst);
             else
-                fout[(size_t)i * ps + o] = r;
+                *dst = r;
         });
     }
     if constexpr (F)
@@ -231,18 +269,18 @@ __global__ __launch_bounds__(kBlock) void k_shift_rows4(StepArgs a) {
         for (int m = 0; m < 4; ++m) collide<L, N, S, T>(v[m], om);
         const uint32_t cell = row * (uint32_t)nx + (uint32_t)x0;
         const size_t o = (size_t)row * rs + (size_t)x0;
-        uint32_t h[4] = {0u, 0u, 0u, 0u};
+        CellBits h[4] = {};
         if constexpr (SR) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) h[m] = mix32((cell + (uint32_t)m) ^ a.sr_key);
+            for (int m = 0; m < 4; ++m) h[m] = cell_bits(cell + (uint32_t)m, a.sr_key);
         }
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             rv4 r;
-            r.x = C::template enc<SR>(v[0][i], SR ? pop_bits(h[0], i) : 0u);
-            r.y = C::template enc<SR>(v[1][i], SR ? pop_bits(h[1], i) : 0u);
-            r.z = C::template enc<SR>(v[2][i], SR ? pop_bits(h[2], i) : 0u);
-            r.w = C::template enc<SR>(v[3][i], SR ? pop_bits(h[3], i) : 0u);
+            r.x = C::template enc<SR>(v[0][i], SR ? pop_bits<i>(h[0]) : 0u);
+            r.y = C::template enc<SR>(v[1][i], SR ? pop_bits<i>(h[1]) : 0u);
+            r.z = C::template enc<SR>(v[2][i], SR ? pop_bits<i>(h[2]) : 0u);
+            r.w = C::template enc<SR>(v[3][i], SR ? pop_bits<i>(h[3]) : 0u);
             __builtin_nontemporal_store(r, reinterpret_cast<rv4 *>(fout + (size_t)i * ps + o));
         });
     }
@@ -281,11 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
         } else {
             collide<L, N, S, T>(v, (T)a.omega);
         }
-        const uint32_t h = SR ? mix32(cell ^ a.sr_key) : 0u;
+        CellBits hb{0u, 0u};
+        if constexpr (SR) hb = cell_bits(cell, a.sr_key);
         const size_t o = (size_t)t * rs + (size_t)x;
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
+            fout[(size_t)i * ps + o] = C::template enc<SR>(v[i], SR ? pop_bits<i>(hb) : 0u);
         });
     }
     if constexpr (F)
@@ -301,13 +340,53 @@ __global__ __launch_bounds__(kBlock) void k_shift_cells(StepArgs a) {
 // single cache line and enter the shift as the value of the vacated lane.  So every
 // population-row costs one aligned load, one one-line halo load and three lane shifts; stores
 // are whole aligned wave segments (non-temporal with NTS: the output is not read again in this
-// step).  With ALT the odd strips walk up (decreasing y) and the even ones down, so two strips
+// step; with NTL the loads of the stencil's own column are non-temporal too, the halo columns'
+// loads, which the neighbouring wave re-reads, not).  With ALT the odd strips walk up (decreasing y) and the even ones down, so two strips
 // start and end at their shared edges at the same time and the rows there, which both read,
 // meet in the L2 instead of being fetched twice; the window slides either way (for a population
 // whose stencil points along the walk it holds rows y, y + d and loads y + 2d, otherwise it
 // holds y - 2d, y - d and loads y).
 // With F the collision adds the body force (force axis y) and the stress sums are stored.
-template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT>
+// Raw buffer accesses: a 128-bit resource (base address, size in bytes) in scalar registers, a
+// 32-bit lane offset and a 32-bit scalar offset, added by the memory unit.  Out-of-range
+// loads return zero and out-of-range stores are dropped (the kernels never issue one).
+constexpr int kBufWord3 = 0x00020000;   // gfx9 family: raw (untyped) 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
+}
+template <class R, bool NT = false>
+__device__ __forceinline__ R buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    constexpr int aux = NT ? 2 : 0;   // 2: non-temporal
+    if constexpr (sizeof(R) == 2)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, aux));
+    else if constexpr (sizeof(R) == 4)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
+    else
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, aux));
+}
+template <bool NT, class R>
+__device__ __forceinline__ void buf_store(R v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    constexpr int aux = NT ? 2 : 0;   // 2: non-temporal
+    if constexpr (sizeof(R) == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, aux);
+    else if constexpr (sizeof(R) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, aux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                              r, voff, soff, aux);
+}
+
+// Beam-Warming coefficients depend on |xi_ad| only: population i reads those of the first
+// population with the same |xi_ad|, so a kernel holds one (alpha, beta) per distinct magnitude
+// (2 per axis for a 4-point Gauss-Hermite product, 3 for 6 points) instead of one per population.
+template <class L>
+constexpr int bw_slot(int i, int d) {
+    for (int j = 0; j < L::Q; ++j)
+        if (L::xi[j][d] == L::xi[i][d] || L::xi[j][d] == -L::xi[i][d]) return j;
+    return i;
+}
+
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false>
 __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
     using C = Codec<S>;
@@ -330,25 +409,31 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     const bool owner = xo < nx;
     const int y0 = (int)(strip * a.tile);
     const int y1 = min(y0 + (int)a.tile, ny);
-    const raw *__restrict__ fin = static_cast<const raw *>(a.fin);
-    raw *__restrict__ fout = static_cast<raw *>(a.fout);
-    const size_t ps = a.lay.pop;
-    auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * a.lay.row; };
+    // addresses: a buffer resource per grid row (all Q populations of the row, below 2^31 bytes:
+    // host check), the column's byte offset as the lane offset and population * bytes between
+    // populations as the scalar offset, so no per-population address arithmetic runs on the VALU
+    const char *__restrict__ fin = static_cast<const char *>(a.fin);
+    char *__restrict__ fout = static_cast<char *>(a.fout);
+    constexpr uint32_t es = (uint32_t)sizeof(raw);
+    const uint32_t ps = (uint32_t)a.lay.pop * es, rowb = (uint32_t)a.lay.row * es;
+    const uint32_t xlb = (uint32_t)xl * es, hlb = (uint32_t)hl * es, hrb = (uint32_t)hr * es, xob = (uint32_t)xo * es;
+    auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * rowb; };
     auto xadv = [&](auto I, size_t roff) -> T {
         constexpr int i = decltype(I)::value;
-        const raw *p = fin + (size_t)i * ps + roff;
-        const T f0 = (T)C::dec(p[xl]);
+        constexpr int kx = bw_slot<L>(i, 0);
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(fin + roff, rowb);
+        const T f0 = (T)C::dec(buf_load<raw, NTL>(rr, xlb, (uint32_t)i * ps));
         T f1, f2;
         if constexpr (L::xi[i][0] > 0.0) {            // upwind = left: f(x-1), f(x-2)
-            const T h = (T)C::dec(p[hl]);
+            const T h = (T)C::dec(buf_load<raw>(rr, hlb, (uint32_t)i * ps));
             f1 = dpp_shr(h, f0);
             f2 = dpp_shr(dpp_shl(h, h), f1);
         } else {                                      // upwind = right: f(x+1), f(x+2)
-            const T h = (T)C::dec(p[hr]);
+            const T h = (T)C::dec(buf_load<raw>(rr, hrb, (uint32_t)i * ps));
             f1 = dpp_shl(h, f0);
             f2 = dpp_shl(dpp_shr(h, h), f1);
         }
-        return f0 - cf.alpha[0][i] * (f0 - f1) + cf.beta[0][i] * (f1 - f2);
+        return f0 - cf.alpha[0][kx] * (f0 - f1) + cf.beta[0][kx] * (f1 - f2);
     };
     const T om = (T)a.omega;
     double ss = 0.0, sc = 0.0;
@@ -374,15 +459,16 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
             const size_t r0 = row_of(y), r2 = row_of(y + 2 * D);
             static_for<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
+                constexpr int ky = bw_slot<L>(i, 1);
                 constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
                 if constexpr (along) {             // A = row y, B = row y+D, new row y+2D
                     const T Cn = xadv(I, r2);
-                    v[i] = A[i] - cf.alpha[1][i] * (A[i] - B[i]) + cf.beta[1][i] * (B[i] - Cn);
+                    v[i] = A[i] - cf.alpha[1][ky] * (A[i] - B[i]) + cf.beta[1][ky] * (B[i] - Cn);
                     A[i] = B[i];
                     B[i] = Cn;
                 } else {                           // A = row y-2D, B = row y-D, new row y
                     const T Cn = xadv(I, r0);
-                    v[i] = Cn - cf.alpha[1][i] * (Cn - B[i]) + cf.beta[1][i] * (B[i] - A[i]);
+                    v[i] = Cn - cf.alpha[1][ky] * (Cn - B[i]) + cf.beta[1][ky] * (B[i] - A[i]);
                     A[i] = B[i];
                     B[i] = Cn;
                 }
@@ -398,15 +484,13 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
                 collide<L, N, S, T>(v, om);
             }
             if (owner) {
-                const size_t o = r0 + (size_t)xo;
-                const uint32_t h = SR ? mix32((uint32_t)(y * nx + xo) ^ a.sr_key) : 0u;
+                const __amdgpu_buffer_rsrc_t wr = make_rsrc(fout + r0, rowb);
+                CellBits hb{0u, 0u};
+                if constexpr (SR) hb = cell_bits((uint32_t)(y * nx + xo), a.sr_key);
                 static_for<L::Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    const raw r = C::template enc<SR>(v[i], SR ? pop_bits(h, i) : 0u);
-                    if constexpr (NTS)
-                        __builtin_nontemporal_store(r, fout + (size_t)i * ps + o);
-                    else
-                        fout[(size_t)i * ps + o] = r;
+                    const raw r = C::template enc<SR>(v[i], SR ? pop_bits<i>(hb) : 0u);
+                    buf_store<NTS>(r, wr, xob, (uint32_t)i * ps);
                 });
             }
         }
@@ -497,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_encode(void *fv, Layout lay, uint32_
     if (cell >= ncell) return;
     auto *f = static_cast<typename C::raw *>(fv);
     const double v = (in[cell] - add) * scale;
-    f[lay.at(a, cell)] = C::template enc<SR>((typename C::T)v, SR ? pop_bits(mix32(cell ^ key), a) : 0u);
+    f[lay.at(a, cell)] = C::template enc<SR>((typename C::T)v, SR ? pop_bits_rt(cell_bits(cell, key), a) : 0u);
 }
 
 // Index of a cell along the force axis.
@@ -605,9 +689,9 @@ hipError_t launch_shift_cells(const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_shift_cells<L, N, S, SR, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
-template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT>
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false>
 hipError_t launch_bw2(const StepArgs &a, const BWCoef<T> &cf, hipStream_t s) {
-    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F, NTS, ALT>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
+    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
     return hipGetLastError();
 }
 template <class L, int N, int S>
@@ -683,11 +767,13 @@ KernelSet make_set() {
             k.bw2_f64[0] = &launch_bw2<L, N, S, SR, double, false, false, false>;
             k.bw2_f64[1] = &launch_bw2<L, N, S, SR, double, false, true, false>;
             k.bw2_f64[2] = &launch_bw2<L, N, S, SR, double, false, true, true>;
+            k.bw2_f64[3] = &launch_bw2<L, N, S, SR, double, false, true, true, true>;
             k.bw2_f64_forced = &launch_bw2<L, N, S, SR, double, true, false, false>;
         } else {
             k.bw2_f32[0] = &launch_bw2<L, N, S, SR, float, false, false, false>;
             k.bw2_f32[1] = &launch_bw2<L, N, S, SR, float, false, true, false>;
             k.bw2_f32[2] = &launch_bw2<L, N, S, SR, float, false, true, true>;
+            k.bw2_f32[3] = &launch_bw2<L, N, S, SR, float, false, true, true, true>;
             k.bw2_f32_forced = &launch_bw2<L, N, S, SR, float, true, false, false>;
         }
     }

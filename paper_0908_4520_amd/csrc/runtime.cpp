@@ -116,13 +116,14 @@ const ShiftTile kShiftTiles[] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256,
                                  {3, 256, 2}};
 constexpr int kPlainShiftTiles = 9;   // without the vector tiles
 // Beam-Warming: rows per strip and variant (0: plain stores, 1: non-temporal stores, 2: non-temporal
-// stores and alternating walk directions of neighbouring strips).  The forced kernel exists for
-// variant 0 only: the first kForcedBWTiles tiles.
+// stores and alternating walk directions of neighbouring strips, 3: variant 2 with non-temporal
+// loads of the stencil's own column).  The forced kernel exists for variant 0 only: the first
+// kForcedBWTiles tiles.
 struct BWTile {
     int rows, variant;
 };
-const BWTile kBWTiles[] = {{16, 0}, {32, 0}, {8, 0}, {4, 0},  {64, 0}, {16, 1}, {32, 1},
-                           {8, 1},  {16, 2}, {32, 2}, {8, 2}, {4, 2},  {64, 2}};
+const BWTile kBWTiles[] = {{16, 0}, {32, 0}, {8, 0},  {4, 0},  {64, 0},  {16, 1}, {32, 1}, {8, 1},  {16, 2},
+                           {32, 2}, {8, 2},  {4, 2},  {64, 2}, {10, 2},  {12, 2}, {13, 2}, {8, 3},  {16, 3}};
 constexpr int kForcedBWTiles = 5;
 
 }  // namespace
@@ -405,6 +406,8 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     if (move == LBM_MOVE_BW2) {
         if (L->on_lattice) return fail(LBM_EINVAL, "upwind advection is provided for the off-lattice sets");
         if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1], got %g", o.cfl);
+        if ((uint64_t)L->Q * (uint64_t)g.nx * (uint64_t)elem_size(o.storage) >= (1ull << 31))
+            return fail(LBM_EINVAL, "upwind advection needs a grid row of all populations below 2^31 bytes");
     }
     if (move != LBM_MOVE_SHIFT && move != LBM_MOVE_BW2) return fail(LBM_EINVAL, "unknown move %d", (int)move);
     if (o.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
@@ -431,7 +434,10 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     s->esize = elem_size(o.storage);
     s->stream = (hipStream_t)o.hip_stream;
     s->ks = ks;
-    s->rows_ok = move == LBM_MOVE_SHIFT && g.nx >= 256 && g.nx >= L->R && g.ny >= L->R && (L->D == 2 || g.nz >= L->R);
+    // the row-tiled and Beam-Warming kernels address a grid row (all Q populations) with 32-bit offsets
+    const bool row_fits = (uint64_t)L->Q * (uint64_t)g.nx * (uint64_t)elem_size(o.storage) < (1ull << 31);
+    s->rows_ok = move == LBM_MOVE_SHIFT && row_fits && g.nx >= 256 && g.nx >= L->R && g.ny >= L->R &&
+                 (L->D == 2 || g.nz >= L->R);
     s->tile = (o.tile > 0 && o.tile < tile_count(s)) ? o.tile : 0;
     if (L->degree < 2 * eq_order) s->warnings |= LBM_WARN_QUADRATURE;
     if (move == LBM_MOVE_BW2) {

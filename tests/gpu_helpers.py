@@ -104,3 +104,28 @@ def oracle_columns(jobs, workers=16):
         else:
             os.environ["OMP_NUM_THREADS"] = saved
     return [res[k] for k in range(len(jobs))]
+
+
+A_FLOOR = 1e-3     # decay fits end where the oracle amplitude falls below A_FLOOR * u0
+
+
+def decay_window(ref, ns, n_first, u0=1e-3):
+    """Reading of the decay-rate definition (least-squares slope of -ln A_s over n >= ceil(10 tau)):
+    the window runs from ceil(10 tau) to the last record at which the oracle's amplitude is still
+    at least 1e-3 u0.  Below that the amplitude is within a factor 100 of the FP32 amplitude bar
+    (1e-5 u0) and of the noise floor FP32 storage leaves after thousands of steps, so the tail
+    of a fast-decaying wave (some fall to 1e-11 u0 within 5000 steps) would fit the rounding
+    noise, not the decay.  A rate is defined where, over that window, the oracle's amplitude
+    stays positive and decreases at every record (no oscillation or sign change), over at least
+    10 records, and falls by at least 10%; returns (n_first, n_last) or None.  Elsewhere the
+    series themselves are compared."""
+    ref = np.asarray(ref)
+    ns = np.asarray(ns)
+    sel = (ns >= n_first) & (ref >= A_FLOOR * u0)
+    idx = np.nonzero(sel)[0]
+    if len(idx) < 10 or not np.all(np.diff(idx) == 1):
+        return None
+    w = ref[idx]
+    if np.all(w > 0) and np.all(np.diff(w) < 0) and w[-1] <= 0.9 * w[0]:
+        return int(ns[idx[0]]), int(ns[idx[-1]])
+    return None

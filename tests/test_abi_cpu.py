@@ -100,6 +100,7 @@ BAD_INIT = [
     ("D2Q16-GH", 2, 1.0, (4, 4, 1), {"cfl": 1.5}, "cfl"),
     ("D2Q16-GH", 2, 1.0, (4, 4, 1), {"cfl": 0.0}, "cfl"),
     ("D3Q39", 2, 1.0, (2048, 2048, 1024), {}, "2^31"),
+    ("D2Q36-GH", 2, 1.0, (2 ** 30, 1, 1), {"storage": "fp64"}, "below 2^31 bytes"),
     ("D2Q9", 2, 1.0, (4, 4, 1), {"check_every": -1}, "check_every"),
 ]
 
@@ -193,3 +194,46 @@ def test_get_cells_validates_before_device_work(lbm):
     f = np.zeros(9)
     cells = np.array([0], dtype=np.int64)
     assert lbm.lib().lbm_get_cells(None, cells.ctypes.data_as(lbm._I64), 1, lbm._dp(f)) == lbm.LBM_EINVAL
+
+
+def _gf2_rank(m):
+    m = m.copy() % 2
+    r = 0
+    for c in range(m.shape[1]):
+        piv = next((i for i in range(r, m.shape[0]) if m[i, c]), None)
+        if piv is None:
+            continue
+        m[[r, piv]] = m[[piv, r]]
+        for i in range(m.shape[0]):
+            if i != r and m[i, c]:
+                m[i] ^= m[r]
+        r += 1
+    return r
+
+
+def test_stochastic_rounding_bit_windows_pairwise_independent():
+    """The rotation table of the stochastic-rounding bits (kernels_impl.h, kSrRot): population
+    pair k's word is rotl(h1, r1_k) ^ rotl(h2, r2_k), population 2k reads its low 16 bits and
+    2k + 1 its high 16.  For (h1, h2) uniform, the 16-bit windows of any two of the first 40
+    populations are jointly uniform iff the 32 x 64 matrix over GF(2) mapping (h1, h2) to them
+    has rank 32; each window alone is then uniform too (unbiased rounding)."""
+    src = open(os.path.join(ROOT, "paper_0908_4520_amd", "csrc", "kernels_impl.h")).read()
+    body = re.search(r"kSrRot\[20\]\[2\]\s*=\s*\{(.*?)\};", src, re.S).group(1)
+    rot = [tuple(int(v) for v in t) for t in re.findall(r"\{\s*(\d+)\s*,\s*(\d+)\s*\}", body)]
+    assert len(rot) == 20
+
+    def rotl(a):                            # bit i of rotl(h, a) is bit (i - a) mod 32 of h
+        m = np.zeros((32, 32), np.uint8)
+        for i in range(32):
+            m[i, (i - a) % 32] = 1
+        return m
+
+    windows = []
+    for a1, a2 in rot:
+        word = np.hstack([rotl(a1), rotl(a2)])
+        windows.append(word[:16])                       # low half
+        windows.append((rotl(16) @ word % 2)[:16])      # high half (word rotated by 16)
+    for p in range(40):
+        assert _gf2_rank(windows[p]) == 16
+        for q in range(p + 1, 40):
+            assert _gf2_rank(np.vstack([windows[p], windows[q]])) == 32, (p, q)

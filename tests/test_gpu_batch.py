@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import need_gpu, oracle_columns, perm, say
+from gpu_helpers import decay_window, need_gpu, oracle_columns, perm, say
 from oracle import bgk as ob
 from oracle import lattices as OL
 from oracle import linmode
@@ -146,29 +146,6 @@ def _linear_series(lat, tau, ny, steps, every):
         out.append((vs.xi[:, 0] @ f).real)
         f = Mk @ f
     return np.array(out)
-
-
-A_FLOOR = 1e-3     # fit window ends where the oracle amplitude falls below A_FLOOR * A0
-
-
-def decay_window(ref, ns, n_first):
-    """Reading of the decay-rate definition (least-squares slope of -ln A_s over n >= ceil(10 tau)):
-    the window runs from ceil(10 tau) to the last record at which the oracle's amplitude is still
-    at least 1e-3 A0.  Below that the amplitude is within a factor 100 of the FP32 amplitude bar
-    (1e-5 A0) and of the noise floor FP32 storage leaves after thousands of steps, so the tail
-    of a fast-decaying instance (some fall to 1e-11 A0 within the 5000 steps) would fit the
-    rounding noise, not the decay.  A rate is defined where, over that window, the oracle's
-    amplitude stays positive and decreases at every record (no oscillation or sign change),
-    over at least 10 records, and falls by at least 10%; returns (n_first, n_last) or None.
-    Elsewhere the series themselves are compared."""
-    sel = (ns >= n_first) & (ref >= A_FLOOR * A0)
-    idx = np.nonzero(sel)[0]
-    if len(idx) < 10 or not np.all(np.diff(idx) == 1):
-        return None
-    w = ref[idx]
-    if np.all(w > 0) and np.all(np.diff(w) < 0) and w[-1] <= 0.9 * w[0]:
-        return int(ns[idx[0]]), int(ns[idx[-1]])
-    return None
 
 
 def test_kn_sweep_256_instances_5000_steps():
