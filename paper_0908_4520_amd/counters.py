@@ -41,8 +41,22 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def shape_key(block: int, blocks: int, nontemporal: bool, vector: int = 1) -> str:
-    return f"{block}x{blocks}" + (":nt" if nontemporal else "") + (f":v{vector}" if vector > 1 else "")
+def shape_key(block: int, blocks: int, nontemporal: bool, vector: int = 1, extra: str = "") -> str:
+    return f"{block}x{blocks}" + (":nt" if nontemporal else "") + (f":v{vector}" if vector > 1 else "") + extra
+
+
+def _bw_extra(name: str) -> str:
+    """k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL>: alternating strip walks and non-temporal loads,
+    which the launch shape alone does not tell apart."""
+    if "k_bw2<" not in name:
+        return ""
+    args = _template_args(name)
+    out = ""
+    if len(args) >= 8 and args[7] == "true":
+        out += ":alt"
+    if len(args) >= 9 and args[8] == "true":
+        out += ":ntl"
+    return out
 
 
 def _template_args(name: str):
@@ -56,6 +70,8 @@ def _nontemporal(name: str) -> bool:
     if "k_shift_rows4<" in name:
         return True
     args = _template_args(name)
+    if "k_bw2<" in name:
+        return len(args) >= 7 and args[6] == "true"
     return "k_shift_rows<" in name and len(args) >= 6 and args[5] == "true"
 
 
@@ -149,7 +165,7 @@ def cmd_traffic(args):
                    "dispatches": len(fetch[key])}
             if args.alg_read_bytes:
                 ent["fetch_over_algorithmic_read"] = round(rd / args.alg_read_bytes, 4)
-            shapes[shape_key(wg, nb, ent["nontemporal"], ent["vector"])] = ent
+            shapes[shape_key(wg, nb, ent["nontemporal"], ent["vector"], _bw_extra(name))] = ent
     if args.json:
         if not shapes:
             raise SystemExit(f"no kernel matches {args.kernel!r}")
