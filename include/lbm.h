@@ -249,6 +249,21 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t tile);
 lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads, int32_t *cells_per_thread,
                          int32_t *vector_width, int64_t *blocks, int32_t *nontemporal);
 lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile, double *best_ms);
+/* lbm_autotune with a persistent cache in the text file `path` (JSON lines, one choice each:
+ * {"key": k, "tile": t, "shape": d, "ms": m}).  The key names the device architecture (HIP's
+ * gcnArchName), lattice, eq_order, storage, rounding, move, whether the body force is on, and the
+ * grid class: ceil(log2 nx), ceil(log2 (ny nz)) and whether nx is a multiple of 256 (grids of one
+ * class share their best tile).  If the file holds the key, and the tile it names is valid for
+ * this simulation and the library still describes that tile's launch as d, the tile is set
+ * without timing: *hit = 1, *best_ms = m (the time stored when it was tuned).  Otherwise the
+ * choice is tuned as by lbm_autotune, *hit = 0, and the file is rewritten with the new line
+ * (replacing an older one of the same key) into a temporary file beside it that is renamed over
+ * it: a reader never sees a torn file, and of two processes storing at once the later rename
+ * wins.  A missing file is an empty cache; lines that do not parse are dropped on rewrite.
+ * LBM_EINVAL for a NULL sim or path or steps_per_trial < 1, and if the file cannot be read or
+ * written (the tuned tile is set all the same).  Output pointers may be NULL. */
+lbm_status lbm_autotune_cached(lbm_sim *s, const char *path, int32_t steps_per_trial, int32_t *best_tile,
+                               double *best_ms, int32_t *hit);
 
 /* Information: cells, populations and bytes moved per step (2 Q ncell * bytes per value). */
 lbm_status lbm_sizes(const lbm_sim *s, int64_t *ncell, int32_t *Q, int32_t *D, int64_t *bytes_per_step);
@@ -303,10 +318,25 @@ lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f);
  * nothing, switches the batch to form 1 and runs in that form.  Workgroup size 256, 512 or
  * 1024.  lbm_batch_set_form picks one; lbm_batch_autotune times every (form, size) pair over
  * `steps` steps, keeps the fastest and restores the state as it was; lbm_batch_form reports
- * the form and size in use. */
+ * the form and size in use.  The grid forms deal chunks to workgroups by a cost model (a fixed
+ * cost per chunk plus a cost per cell and velocity set); for each grid (form, size) the autotuner
+ * also takes a step profile (as lbm_batch_profile), fits the model's costs to the workgroups'
+ * measured times by non-negative least squares, plans again with them, times that plan, and keeps
+ * the fitted costs for that (form, size) only if they run faster.  The plan never changes what
+ * is computed: every cell is stepped by the same arithmetic in every form and plan. */
 lbm_status lbm_batch_set_form(lbm_batch *b, int32_t form, int32_t block);
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_t *block, double *ms_per_step);
 lbm_status lbm_batch_form(const lbm_batch *b, int32_t *form, int32_t *block);
+/* The autotuner's calibration step for the form and size in use (grid forms only): a step
+ * profile of `steps` >= 1 steps, the cost model fitted to it, and the batch planned with the
+ * fitted costs (kept for this form and size until a later calibration or autotune replaces them).
+ * The state is left as it was.  costs (may be NULL) receives *ncosts = K + 1 values: the fitted
+ * cost per cell of each of the K velocity sets present (in order of their first instance), then
+ * the cost per chunk (device clock ticks).  steps = 0 drops the fitted costs of this form and size
+ * (back to the default model; costs receives zeros).  LBM_EINVAL in form 0 or for steps < 0;
+ * LBM_EDEVICE if the profile did not complete as planned or nothing could be fitted (the default
+ * model then stays). */
+lbm_status lbm_batch_calibrate(lbm_batch *b, int32_t steps, double *costs, int32_t *ncosts);
 /* Testing hook of form 2's fallback: plan it for nxcd XCDs (1..16) instead of the number a probe
  * launch finds (nxcd = 0 restores the probe).  A plan for fewer XCDs than the device has leaves
  * the workgroups of the other XCDs without a slot; the next lbm_batch_run sees that before any
@@ -318,6 +348,18 @@ lbm_status lbm_batch_plan_xcds(lbm_batch *b, int32_t nxcd);
  * tiny bound makes waits expire and exercises the undefined-state rule above; every workgroup
  * still leaves normally. */
 lbm_status lbm_batch_set_spin_limit(lbm_batch *b, uint32_t limit);
+/* Step profile of the grid forms (1 and 2): advances every instance by `steps` >= 1 steps as
+ * lbm_batch_run does (no amplitudes, no graph), and every workgroup of the persistent grid
+ * stores three timestamps of the device's constant 100 MHz clock for each of the steps
+ * first .. first + count - 1: when the step started, when the workgroup's chunks were done (all
+ * its threads), and when the step's barrier released it.  ts (host, may be NULL) receives
+ * nwg * count * 3 values, ts[(w * count + k) * 3 + j] for workgroup w of the plan, step first + k,
+ * timestamp j; *nwg receives the number of workgroups (with ts NULL nothing runs: a size query).
+ * The chunk work and barrier wait per step follow as differences, which is what the batch's
+ * load balance is judged by.  LBM_EINVAL in form 0, for an empty or out-of-range step window,
+ * or above 2^28 timestamps; barrier timeouts and the XCD fallback act as in lbm_batch_run, except
+ * that after a fallback nothing was stepped and LBM_EDEVICE is returned (profile again). */
+lbm_status lbm_batch_profile(lbm_batch *b, int64_t steps, int64_t first, int32_t count, int32_t *nwg, uint64_t *ts);
 /* Total cells and algorithmic bytes per step (2 Q ncell x bytes per value, summed). */
 lbm_status lbm_batch_sizes(const lbm_batch *b, int64_t *cells, int64_t *bytes_per_step);
 void lbm_batch_free(lbm_batch *b);   /* NULL-safe */

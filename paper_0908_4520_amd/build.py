@@ -24,7 +24,7 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
 
 
 def sources():
-    return sorted(CSRC.glob("*.hip")) + [CSRC / "runtime.cpp"]
+    return sorted(CSRC.glob("*.hip")) + [CSRC / "runtime.cpp", CSRC / "host_logic.cpp"]
 
 
 def _compile(src: Path) -> Path:

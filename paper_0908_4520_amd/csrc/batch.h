@@ -51,6 +51,13 @@ struct BatchArgs {
     // XCD-local grid form: workgroup slot s on XCD x runs the chunks of plan entry x * wg_per_xcd + s
     uint32_t *sync;             // per-XCD counters, see kSyncWords (zeroed before the launch)
     uint32_t nxcd, wg_per_xcd;
+    // step profile of the grid forms (null = off; non-null launches the profiling kernel): for
+    // steps ts_first .. ts_first + ts_count - 1 every workgroup stores three 100 MHz timestamps,
+    // ts[(entry * ts_count + k) * 3 + {0,1,2}] = step start, its chunks done, the step's barrier
+    // passed (entry = plan entry of the workgroup)
+    uint64_t *ts;
+    int64_t ts_first;
+    int32_t ts_count;
 };
 
 // Per-XCD counters of the XCD-local form, one 128-byte line each: sync[x * kSyncStride] counts

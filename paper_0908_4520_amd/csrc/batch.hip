@@ -298,7 +298,8 @@ __device__ bool xcd_barrier(const BatchArgs &a, uint32_t x, uint64_t gen, int *f
 }
 
 // XCD: false for the device-wide form (plan entry = blockIdx.x), true for the XCD-local form.
-template <int S, int BLOCK, bool XCD>
+// PROF: the step-profile instantiation (timestamps into a.ts); the plain one has none of that code.
+template <int S, int BLOCK, bool XCD, bool PROF = false>
 __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
     __shared__ double red[BLOCK / 64];
     __shared__ int flag;
@@ -344,16 +345,28 @@ __global__ __launch_bounds__(BLOCK) void k_batch_grid(BatchArgs a) {
     if (a.record_first) record(0, 0);
     uint64_t gen = 0;
     for (int64_t step = 0; step < a.steps; ++step) {
+        // step profile: thread 0 stores each timestamp as it is taken (nothing held across the step)
+        const bool prof = PROF && step >= a.ts_first && step < a.ts_first + a.ts_count;
+        auto stamp = [&](int j) {
+            a.ts[((size_t)entry * (size_t)a.ts_count + (size_t)(step - a.ts_first)) * 3 + j] =
+                __builtin_amdgcn_s_memrealtime();
+        };
+        if (prof && threadIdx.x == 0) stamp(0);
         for (uint32_t c = c0; c < c1; ++c) {
             const BatchChunk ch = a.chunks[a.wg_chunks[c]];
             const BatchInst in = a.inst[ch.inst];
             step_chunk<S>(in, a, a.cur[ch.inst] ^ (int)(step & 1), ch.start, ch.count);
+        }
+        if (prof) {
+            __syncthreads();
+            if (threadIdx.x == 0) stamp(1);
         }
         if constexpr (XCD) {
             if (!xcd_barrier(a, xcd, ++gen, &flag)) return;
         } else {
             if (!grid_barrier(a, ++gen, &flag)) return;
         }
+        if (prof && threadIdx.x == 0) stamp(2);
         if (a.record > 0 && (step + 1) % a.record == 0) record((int)((step + 1) / a.record), step + 1);
     }
 }
@@ -396,10 +409,24 @@ hipError_t launch_t(int form, const BatchArgs &a, uint32_t count, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (form == 2)
+    if (a.ts) {
+        // the profile instantiation must fit as many workgroups per CU as the plan assumed
+        int n0 = 0, n1 = 0;
+        const void *k0 = form == 2 ? (const void *)k_batch_grid<S, BLOCK, true> : (const void *)k_batch_grid<S, BLOCK, false>;
+        const void *k1 = form == 2 ? (const void *)k_batch_grid<S, BLOCK, true, true>
+                                   : (const void *)k_batch_grid<S, BLOCK, false, true>;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n0, k0, BLOCK, 0)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, k1, BLOCK, 0)) != hipSuccess) return e;
+        if (n1 < n0) return hipErrorLaunchOutOfResources;
+        if (form == 2)
+            hipLaunchKernelGGL((k_batch_grid<S, BLOCK, true, true>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_batch_grid<S, BLOCK, false, true>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+    } else if (form == 2) {
         hipLaunchKernelGGL((k_batch_grid<S, BLOCK, true>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
-    else
+    } else {
         hipLaunchKernelGGL((k_batch_grid<S, BLOCK, false>), dim3(a.nwg), dim3(BLOCK), 0, s, a);
+    }
     e = hipGetLastError();
     if (e != hipSuccess || (a.record <= 0 && !a.record_first)) return e;
     const uint64_t n = (uint64_t)count * a.nrec;

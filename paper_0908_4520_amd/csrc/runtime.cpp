@@ -7,17 +7,22 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "batch.h"
+#include "host_logic.h"
 #include "kernels.h"
 #include "lattices.inc"
 #include "lbm.h"
 #include "noalloc.h"
 
 using namespace lbm;
+using host::kBWTiles;
+using host::kShiftTiles;
+static_assert(host::kCellBlock == (uint32_t)kBlock, "one-thread-per-cell kernels run kBlock threads");
 
 namespace {
 
@@ -104,27 +109,6 @@ uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-// Step-kernel tile choices.  Shift: kernel variant (0: 256 threads, 1: 256 threads with
-// non-temporal stores, 2: 512 threads with non-temporal stores, 3: 256 threads x 4 cells per
-// thread with vector accesses) and chunks per block (of block threads x cells per thread).
-// Beam-Warming: rows per strip.
-struct ShiftTile {
-    int variant, block, chunks;
-};
-const ShiftTile kShiftTiles[] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256, 8}, {2, 512, 4},
-                                 {2, 512, 2}, {2, 512, 1}, {1, 256, 4}, {1, 256, 8}, {3, 256, 1},
-                                 {3, 256, 2}};
-constexpr int kPlainShiftTiles = 9;   // without the vector tiles
-// Beam-Warming: rows per strip and variant (0: plain stores, 1: non-temporal stores, 2: non-temporal
-// stores and alternating walk directions of neighbouring strips, 3: variant 2 with non-temporal
-// loads of the stencil's own column).  The forced kernel exists for variant 0 only: the first
-// kForcedBWTiles tiles.
-struct BWTile {
-    int rows, variant;
-};
-const BWTile kBWTiles[] = {{16, 0}, {32, 0}, {8, 0},  {4, 0},  {64, 0},  {16, 1}, {32, 1}, {8, 1},  {16, 2},
-                           {32, 2}, {8, 2},  {4, 2},  {64, 2}, {10, 2},  {12, 2}, {13, 2}, {8, 3},  {16, 3}};
-constexpr int kForcedBWTiles = 5;
 
 }  // namespace
 
@@ -175,6 +159,19 @@ double force_g_at(const lbm_sim *s, int64_t n) {
     return s->f_amp * s->f_dt * cos(s->f_freq * (double)n * s->f_dt);
 }
 
+// What the tile choice of a simulation depends on.
+host::StepShape step_shape(const lbm_sim *s) {
+    host::StepShape h{};
+    h.bw2 = s->move == LBM_MOVE_BW2;
+    h.rows_ok = s->rows_ok;
+    h.forced = s->forced;
+    h.vector_ok = s->ks->shift_rows4 != nullptr && s->g.nx % 256 == 0;
+    h.nx = s->g.nx;
+    h.ny = s->g.ny;
+    h.nz = s->g.nz;
+    return h;
+}
+
 StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index) {
     StepArgs a{};
     a.fin = fin;
@@ -185,23 +182,10 @@ StepArgs step_args(const lbm_sim *s, const void *fin, void *fout, int tile_index
     a.lay = s->lay;
     a.omega = s->omega;
     a.sr_key = (uint32_t)splitmix64(s->o.sr_seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(s->nstep + 1)));
-    const uint32_t nx = (uint32_t)s->g.nx;
-    if (s->move == LBM_MOVE_BW2) {
-        const uint32_t H = (uint32_t)kBWTiles[tile_index].rows;
-        a.tile = H;
-        a.per_row = (nx + kBlock - 1) / kBlock;   // blocks of 4 waves x 64 columns
-        a.nblocks = a.per_row * (((uint32_t)s->g.ny + H - 1) / H);
-    } else if (s->rows_ok) {
-        const ShiftTile &t = kShiftTiles[tile_index];
-        const uint32_t cpt = (uint32_t)t.chunks, blk = (uint32_t)t.block * (t.variant == 3 ? 4u : 1u);
-        a.tile = cpt;
-        a.per_row = (nx + blk * cpt - 1) / (blk * cpt);
-        a.nblocks = a.per_row * (uint32_t)s->g.ny * (uint32_t)s->g.nz;
-    } else {
-        a.tile = 1;
-        a.per_row = 1;
-        a.nblocks = (uint32_t)((s->ncell + kBlock - 1) / kBlock);
-    }
+    const host::StepGeom g = host::step_geometry(step_shape(s), tile_index);
+    a.tile = g.tile;
+    a.per_row = g.per_row;
+    a.nblocks = g.nblocks;
     return a;
 }
 
@@ -243,20 +227,7 @@ hipError_t launch_step(lbm_sim *s, const void *fin, void *fout, int tile_index, 
     return v == 3 ? k->shift_rows4(a, s->stream) : k->shift_rows[v](a, s->stream);
 }
 
-// The forced row kernel exists as variants 0 and 2 only: the first seven shift tiles.
-constexpr int kForcedShiftTiles = 7;
-
-// The vector tiles need their kernel (FP32 storages, |c_x| <= 4) and whole 256-cell waves.
-bool vector_tiles_ok(const lbm_sim *s) { return s->ks->shift_rows4 != nullptr && s->g.nx % 256 == 0; }
-
-int tile_count(const lbm_sim *s) {
-    if (s->move == LBM_MOVE_BW2) return s->forced ? kForcedBWTiles : (int)(sizeof kBWTiles / sizeof kBWTiles[0]);
-    if (s->rows_ok) {
-        if (s->forced) return kForcedShiftTiles;
-        return vector_tiles_ok(s) ? (int)(sizeof kShiftTiles / sizeof kShiftTiles[0]) : kPlainShiftTiles;
-    }
-    return 1;
-}
+int tile_count(const lbm_sim *s) { return host::tile_count(step_shape(s)); }
 
 // Host values of the wave tables (host libm): for each wave axis (y, then z for 3-D sets)
 // sin(2 pi j / N_w) then cos(2 pi j / N_w), j < N_w.
@@ -314,12 +285,8 @@ lbm_status run_diag(lbm_sim *s, int axis, double out[6]) {
 // Caller-owned population buffers (lbm_opts.dev_buf): both given, large enough, aligned for
 // the 16-byte vector accesses, disjoint, and device memory of the current device.
 lbm_status check_dev_buffers(const lbm_opts &o, size_t need) {
-    if (!o.dev_buf[0] || !o.dev_buf[1]) return fail(LBM_EINVAL, "dev_buf: give both buffers or neither");
-    if (o.dev_buf_bytes < 0 || (uint64_t)o.dev_buf_bytes < (uint64_t)need)
-        return fail(LBM_EINVAL, "dev_buf: %lld bytes per buffer given, the state needs %zu", (long long)o.dev_buf_bytes, need);
-    const uintptr_t p0 = (uintptr_t)o.dev_buf[0], p1 = (uintptr_t)o.dev_buf[1];
-    if ((p0 | p1) & 15u) return fail(LBM_EINVAL, "dev_buf: buffers must be 16-byte aligned");
-    if ((p0 < p1 ? p1 - p0 : p0 - p1) < need) return fail(LBM_EINVAL, "dev_buf: the two buffers overlap");
+    std::string msg;
+    if (host::check_dev_buf_shape(o, need, &msg) != LBM_OK) return fail(LBM_EINVAL, "%s", msg.c_str());
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
@@ -389,28 +356,15 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     const LatInfo *L = lat_info((int)lat);
     if (!L) return fail(LBM_EINVAL, "unknown lattice %d", (int)lat);
-    if (eq_order < 1 || eq_order > 4) return fail(LBM_EINVAL, "eq_order must be 1..4, got %d", eq_order);
-    if (!(tau > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2 (or +inf), got %g", tau);
-    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(LBM_EINVAL, "grid dimensions must be >= 1");
-    if (L->D == 2 && g.nz != 1) return fail(LBM_EINVAL, "2-D velocity set needs nz = 1, got %d", g.nz);
-    const unsigned long long ncell = (unsigned long long)g.nx * g.ny * g.nz;
-    if (ncell > 0x7fffffffull) return fail(LBM_EINVAL, "grid of %llu cells exceeds 2^31 - 1", ncell);
     lbm_opts o;
     lbm_opts_default(&o);
     if (opts) o = *opts;
-    if (o.storage < LBM_FP64 || o.storage > LBM_BF16_DEV) return fail(LBM_EINVAL, "unknown storage %d", (int)o.storage);
-    lbm_move move = o.move;
-    if (move == LBM_MOVE_AUTO) move = L->on_lattice ? LBM_MOVE_SHIFT : LBM_MOVE_BW2;
-    if (move == LBM_MOVE_SHIFT && !L->on_lattice)
-        return fail(LBM_EINVAL, "exact shift needs an on-lattice velocity set");
-    if (move == LBM_MOVE_BW2) {
-        if (L->on_lattice) return fail(LBM_EINVAL, "upwind advection is provided for the off-lattice sets");
-        if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1], got %g", o.cfl);
-        if ((uint64_t)L->Q * (uint64_t)g.nx * (uint64_t)elem_size(o.storage) >= (1ull << 31))
-            return fail(LBM_EINVAL, "upwind advection needs a grid row of all populations below 2^31 bytes");
-    }
-    if (move != LBM_MOVE_SHIFT && move != LBM_MOVE_BW2) return fail(LBM_EINVAL, "unknown move %d", (int)move);
-    if (o.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+    const host::LatShape shape{L->Q, L->D, L->R, L->on_lattice};
+    lbm_move move = LBM_MOVE_AUTO;
+    std::string msg;
+    if (host::check_init(&shape, eq_order, tau, g, o, host::storage_bytes(o), &move, &msg) != LBM_OK)
+        return fail(LBM_EINVAL, "%s", msg.c_str());
+    const unsigned long long ncell = (unsigned long long)g.nx * g.ny * g.nz;
     const size_t state_bytes = (size_t)L->Q * (size_t)ncell * (size_t)elem_size(o.storage);
     const bool given = o.dev_buf[0] != nullptr || o.dev_buf[1] != nullptr;
     if (given) {
@@ -435,9 +389,7 @@ lbm_status lbm_init_ex(lbm_sim **out, lbm_lattice lat, int32_t eq_order, double 
     s->stream = (hipStream_t)o.hip_stream;
     s->ks = ks;
     // the row-tiled and Beam-Warming kernels address a grid row (all Q populations) with 32-bit offsets
-    const bool row_fits = (uint64_t)L->Q * (uint64_t)g.nx * (uint64_t)elem_size(o.storage) < (1ull << 31);
-    s->rows_ok = move == LBM_MOVE_SHIFT && row_fits && g.nx >= 256 && g.nx >= L->R && g.ny >= L->R &&
-                 (L->D == 2 || g.nz >= L->R);
+    s->rows_ok = host::row_tiles_ok(move == LBM_MOVE_SHIFT, L->Q, L->D, L->R, g, elem_size(o.storage));
     s->tile = (o.tile > 0 && o.tile < tile_count(s)) ? o.tile : 0;
     if (L->degree < 2 * eq_order) s->warnings |= LBM_WARN_QUADRATURE;
     if (move == LBM_MOVE_BW2) {
@@ -890,15 +842,15 @@ lbm_status lbm_tile_info(const lbm_sim *s, int32_t tile, int32_t *block_threads,
                          int32_t *vector_width, int64_t *blocks, int32_t *nontemporal) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (tile < 0 || tile >= tile_count(s)) return fail(LBM_EINVAL, "tile %d out of range [0, %d)", tile, tile_count(s));
-    const StepArgs a = step_args(s, s->buf[0], s->buf[1], tile);
-    const bool rows = s->move != LBM_MOVE_BW2 && s->rows_ok;
-    if (block_threads) *block_threads = rows ? kShiftTiles[tile].block : kBlock;
-    const int32_t vw = rows && kShiftTiles[tile].variant == 3 ? 4 : 1;
-    if (cells_per_thread) *cells_per_thread = (int32_t)a.tile * vw;
+    const host::StepShape h = step_shape(s);
+    int blk = 0, cpt = 0, vw = 0;
+    bool nt = false;
+    host::tile_launch(h, tile, &blk, &cpt, &vw, &nt);
+    if (block_threads) *block_threads = blk;
+    if (cells_per_thread) *cells_per_thread = cpt;
     if (vector_width) *vector_width = vw;
-    if (blocks) *blocks = (int64_t)a.nblocks;
-    if (nontemporal)
-        *nontemporal = rows ? kShiftTiles[tile].variant != 0 : (s->move == LBM_MOVE_BW2 && kBWTiles[tile].variant != 0);
+    if (blocks) *blocks = (int64_t)host::step_geometry(h, tile).nblocks;
+    if (nontemporal) *nontemporal = nt ? 1 : 0;
     return LBM_OK;
 }
 
@@ -946,6 +898,38 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t steps_per_trial, int32_t *best_tile,
     return LBM_OK;
 }
 
+lbm_status lbm_autotune_cached(lbm_sim *s, const char *path, int32_t steps_per_trial, int32_t *best_tile,
+                               double *best_ms, int32_t *hit) {
+    if (!s || !path || !*path) return fail(LBM_EINVAL, "sim or path is NULL");
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    hipDeviceProp_t prop{};
+    HIP_TRY(hipGetDeviceProperties(&prop, s->device));
+    const host::StepShape h = step_shape(s);
+    const std::string key = host::tune_key(prop.gcnArchName, s->L->id, s->N, (int)s->o.storage, s->ks->sr, h);
+    host::TuneEntry e;
+    if (host::tune_lookup(path, key, &e) && e.tile >= 0 && e.tile < tile_count(s) && e.shape == host::tile_shape(h, e.tile)) {
+        s->tile = e.tile;
+        if (best_tile) *best_tile = e.tile;
+        if (best_ms) *best_ms = e.ms;
+        if (hit) *hit = 1;
+        return LBM_OK;
+    }
+    int32_t t = 0;
+    double ms = 0;
+    const lbm_status st = lbm_autotune(s, steps_per_trial, &t, &ms);
+    if (st != LBM_OK) return st;
+    if (best_tile) *best_tile = t;
+    if (best_ms) *best_ms = ms;
+    if (hit) *hit = 0;
+    e.key = key;
+    e.tile = t;
+    e.shape = host::tile_shape(h, t);
+    e.ms = ms;
+    std::string err;
+    if (!host::tune_store(path, e, &err)) return fail(LBM_EINVAL, "autotuner cache: %s", err.c_str());
+    return LBM_OK;
+}
+
 }  // extern "C"
 
 // ======================================================================== batches
@@ -973,8 +957,14 @@ struct lbm_batch {
                                             // 2: chunks + barrier per XCD
     int block = 512;
     int64_t cells = 0, bytes_per_step = 0;
-    // grid-form plan (for plan_block, plan_form)
+    // grid-form plan (for plan_block, plan_form; host copy in plan)
     int plan_block = 0, plan_form = 0;
+    host::BatchPlan plan;
+    std::vector<int> kind;                  // per instance: index of its velocity set among those present
+    int nkinds = 0;
+    // chunk costs fitted by the autotuner per (form, block): per-cell cost of each kind, then the
+    // per-chunk cost (absent: the default model)
+    std::map<std::pair<int, int>, std::vector<double>> cal;
     uint32_t nchunks = 0, nwg = 0;
     int nxcd = 0;                           // XCDs seen by the probe (0: not probed, -1: form 2 unusable)
     int xcd_force = 0;                      // plan form 2 for this many XCDs instead (testing; 0 = probe)
@@ -1034,23 +1024,6 @@ lbm_status realloc_dev(P **p, size_t bytes) {
     return LBM_OK;
 }
 
-// Longest-processing-time-first: items (largest cost first) onto the least-loaded of n bins.
-std::vector<std::vector<uint32_t>> lpt(const std::vector<uint32_t> &items, const std::vector<double> &cost, uint32_t n) {
-    std::vector<uint32_t> idx(items);
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
-    std::vector<double> load(n, 0.0);
-    std::vector<std::vector<uint32_t>> lists(n);
-    for (uint32_t k : idx) {
-        uint32_t best = 0;
-        for (uint32_t w = 1; w < n; ++w)
-            if (load[w] < load[best]) best = w;
-        load[best] += cost[k];
-        lists[best].push_back(k);
-    }
-    for (auto &l : lists) std::sort(l.begin(), l.end());
-    return lists;
-}
-
 // Number of XCDs, from the XCD ids of a probe launch of n workgroups (the grid size of the
 // XCD-local form); -1 if the workgroups were not spread evenly over them.
 lbm_status batch_probe_xcd(lbm_batch *b, uint32_t n) {
@@ -1087,62 +1060,27 @@ lbm_status batch_plan(lbm_batch *b, int block, int form) {
     if (form == 2) {
         if (b->nxcd == 0 && (st = batch_probe_xcd(b, resident)) != LBM_OK) return st;
         if (b->nxcd < 1) return fail(LBM_EDEVICE, "workgroups are not spread evenly over XCDs: XCD-local form unusable");
-    }
-    std::vector<BatchChunk> chunks;
-    std::vector<uint32_t> inst_first(b->count + 1, 0);
-    std::vector<double> cost;
-    for (int i = 0; i < b->count; ++i) {
-        inst_first[i] = (uint32_t)chunks.size();
-        const BatchInst &d = b->desc[i];
-        const LatInfo *L = lat_info(d.lattice);
-        // time per cell of one step, fitted to per-instance runs of one 512-thread workgroup per
-        // CU on MI355X (ns): D2Q9 4.0, D2Q37 8.8 (exact shift), D2Q16-GH 11.5, D2Q36-GH 25
-        // (Beam-Warming reads three rows per population and applies two difference stencils)
-        const double per_cell = L->on_lattice ? 2.5 + 0.17 * L->Q : 0.7 + 0.68 * L->Q;
-        for (uint32_t s0 = 0; s0 < d.ncell; s0 += (uint32_t)block) {
-            const uint32_t n = std::min<uint32_t>((uint32_t)block, d.ncell - s0);
-            chunks.push_back(BatchChunk{i, s0, n});
-            cost.push_back(per_cell * n);
-        }
-    }
-    inst_first[b->count] = (uint32_t)chunks.size();
-    const uint32_t nchunks = (uint32_t)chunks.size();
-    std::vector<std::vector<uint32_t>> lists;
-    uint32_t nwg = 0, per_xcd = 0;
-    if (form == 2) {
         const uint32_t nx = (uint32_t)(b->xcd_force > 0 ? b->xcd_force : b->nxcd);
-        std::vector<uint32_t> insts(b->count);
-        std::vector<double> icost(b->count, 0.0);
-        for (int i = 0; i < b->count; ++i) {
-            insts[i] = (uint32_t)i;
-            for (uint32_t c = inst_first[i]; c < inst_first[i + 1]; ++c) icost[i] += cost[c];
-        }
-        const auto bins = lpt(insts, icost, nx);
-        size_t most = 1;
-        std::vector<std::vector<uint32_t>> xchunks(nx);
-        for (uint32_t x = 0; x < nx; ++x) {
-            for (uint32_t i : bins[x])
-                for (uint32_t c = inst_first[i]; c < inst_first[i + 1]; ++c) xchunks[x].push_back(c);
-            most = std::max(most, xchunks[x].size());
-        }
-        per_xcd = (uint32_t)std::min<size_t>(most, std::max<uint32_t>(1u, resident / nx));
-        nwg = per_xcd * nx;
-        for (uint32_t x = 0; x < nx; ++x) {
-            auto part = lpt(xchunks[x], cost, per_xcd);
-            for (auto &l : part) lists.push_back(std::move(l));
-        }
-    } else {
-        nwg = std::min<uint32_t>(nchunks, resident);
-        std::vector<uint32_t> all(nchunks);
-        for (uint32_t k = 0; k < nchunks; ++k) all[k] = k;
-        lists = lpt(all, cost, nwg);
+        if (resident < nx) return fail(LBM_EDEVICE, "XCD-local form needs a resident workgroup per XCD");
     }
-    std::vector<uint32_t> wg_first(nwg + 1, 0), wg_chunks;
-    for (uint32_t w = 0; w < nwg; ++w) {
-        wg_first[w] = (uint32_t)wg_chunks.size();
-        wg_chunks.insert(wg_chunks.end(), lists[w].begin(), lists[w].end());
+    std::vector<uint32_t> ncell(b->count);
+    std::vector<double> per_cell(b->count);
+    double per_chunk = 0.0;
+    const auto c = b->cal.find({form, block});
+    for (int i = 0; i < b->count; ++i) {
+        const LatInfo *L = lat_info(b->desc[i].lattice);
+        ncell[i] = b->desc[i].ncell;
+        per_cell[i] = c != b->cal.end() ? c->second[b->kind[i]] : host::batch_cell_cost(L->on_lattice, L->Q);
     }
-    wg_first[nwg] = (uint32_t)wg_chunks.size();
+    if (c != b->cal.end()) per_chunk = c->second[b->nkinds];
+    const uint32_t nx = form == 2 ? (uint32_t)(b->xcd_force > 0 ? b->xcd_force : b->nxcd) : 1u;
+    b->plan = host::plan_batch(ncell, per_cell, per_chunk, (uint32_t)block, form, resident, nx);
+    const host::BatchPlan &plan = b->plan;
+    const uint32_t nchunks = (uint32_t)plan.chunks.size(), nwg = plan.nwg, per_xcd = plan.per_xcd;
+    std::vector<BatchChunk> chunks(nchunks);
+    for (uint32_t k = 0; k < nchunks; ++k)
+        chunks[k] = BatchChunk{plan.chunks[k].inst, plan.chunks[k].start, plan.chunks[k].count};
+    const std::vector<uint32_t> &inst_first = plan.inst_first, &wg_first = plan.wg_first, &wg_chunks = plan.wg_chunks;
     if ((st = realloc_dev(&b->d_chunks, sizeof(BatchChunk) * nchunks)) != LBM_OK) return st;
     if ((st = realloc_dev(&b->d_inst_first, sizeof(uint32_t) * inst_first.size())) != LBM_OK) return st;
     if ((st = realloc_dev(&b->d_wg_first, sizeof(uint32_t) * wg_first.size())) != LBM_OK) return st;
@@ -1221,6 +1159,64 @@ lbm_status batch_abort_flag(lbm_batch *b, int32_t *ab) {
     return LBM_OK;
 }
 
+// One step-profile launch of the current plan (form b->form, workgroup size b->block): steps
+// steps from the state on the device, timestamps of steps first .. first + count - 1 into ts
+// (host, nwg * count * 3).  *ab receives the launch's abort flag.  Does not flip b->cur.
+lbm_status batch_profile_launch(lbm_batch *b, int64_t steps, int64_t first, int32_t count, uint64_t *ts, int32_t *ab) {
+    lbm_status st;
+    if ((st = batch_ensure_logs(b, 1)) != LBM_OK) return st;
+    for (int i = 0; i < b->count; ++i) b->desc[i].amp_off = (uint64_t)i;
+    batch_drop_graph(b);
+    const size_t n_ts = (size_t)b->nwg * (size_t)count * 3;
+    uint64_t *d_ts = nullptr;
+    HIP_TRY(hipMalloc(&d_ts, sizeof(uint64_t) * n_ts));
+    BatchArgs a = batch_args(b, steps, 0, 0, 1);
+    a.ts = d_ts;
+    a.ts_first = first;
+    a.ts_count = count;
+    hipError_t e = hipMemcpyAsync(b->d_inst, b->desc.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_cur, b->cur.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = launch_batch((int)b->storage, b->form, b->block, a, (uint32_t)b->count, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ts, d_ts, sizeof(uint64_t) * n_ts, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(d_ts);
+    HIP_TRY(e);
+    return batch_abort_flag(b, ab);
+}
+
+// Fit the chunk costs of the current (form, block) to a step profile of `steps` steps (the state
+// is stepped; the caller restores it).  On success the fitted costs are stored in b->cal and the
+// batch is planned with them; *ok = false leaves the plan as it was.
+lbm_status batch_calibrate(lbm_batch *b, int64_t steps, bool *ok) {
+    *ok = false;
+    const int32_t count = (int32_t)std::min<int64_t>(64, steps);
+    const int64_t first = (steps - count) / 2;
+    std::vector<uint64_t> ts((size_t)b->nwg * (size_t)count * 3);
+    int32_t ab = 0;
+    lbm_status st = batch_profile_launch(b, steps, first, count, ts.data(), &ab);
+    if (st != LBM_OK || ab) return st;
+    // per workgroup: median over the profiled steps of start-to-chunks-done
+    std::vector<double> work(b->nwg), tmp(count);
+    for (uint32_t w = 0; w < b->nwg; ++w) {
+        for (int32_t k = 0; k < count; ++k) {
+            const uint64_t *t = &ts[((size_t)w * count + k) * 3];
+            tmp[k] = (double)(t[1] - t[0]);
+        }
+        std::nth_element(tmp.begin(), tmp.begin() + count / 2, tmp.end());
+        work[w] = tmp[count / 2];
+    }
+    const std::vector<double> coef = host::fit_chunk_costs(b->plan, b->kind, b->nkinds, work);
+    bool any = false;
+    for (int k = 0; k <= b->nkinds; ++k) any = any || coef[k] > 0;
+    if (!any) return LBM_OK;   // nothing fitted: keep the default model
+    b->cal[{b->form, b->block}] = coef;
+    b->plan_block = 0;
+    if ((st = batch_plan(b, b->block, b->form)) != LBM_OK) return st;
+    *ok = true;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1232,8 +1228,9 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
     lbm_opts_default(&o);
     o.storage = LBM_FP32_DEV;
     if (opts) o = *opts;
-    if (o.storage != LBM_FP32_DEV && o.storage != LBM_FP64)
-        return fail(LBM_EINVAL, "batches store LBM_FP32_DEV or LBM_FP64");
+    int32_t storage = 0;   // read as the int a C caller passed (it may be outside the enumeration)
+    memcpy(&storage, &o.storage, sizeof storage);
+    if (storage != LBM_FP32_DEV && storage != LBM_FP64) return fail(LBM_EINVAL, "batches store LBM_FP32_DEV or LBM_FP64");
     if (o.dev_buf[0] || o.dev_buf[1]) return fail(LBM_EINVAL, "batches allocate their own pool: dev_buf must be NULL");
     if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(LBM_EINVAL, "cfl must be in (0, 1]");
     for (int i = 0; i < count; ++i) {
@@ -1290,6 +1287,16 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_instance *inst, int32_t c
         b->cells += d.ncell;
         b->bytes_per_step += 2ll * L->Q * d.ncell * es;
     }
+    // kinds for the fitted cost model: the distinct velocity sets, in order of appearance
+    std::vector<int> kind_lat;
+    b->kind.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const int id = b->desc[i].lattice;
+        auto it = std::find(kind_lat.begin(), kind_lat.end(), id);
+        if (it == kind_lat.end()) it = kind_lat.insert(kind_lat.end(), id);
+        b->kind[i] = (int)(it - kind_lat.begin());
+    }
+    b->nkinds = (int)kind_lat.size();
     // per-instance form: workgroups take instances largest first (cost ~ Q * cells)
     std::vector<int32_t> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -1436,6 +1443,34 @@ lbm_status lbm_batch_run(lbm_batch *b, int64_t steps, int32_t record_every, doub
     return LBM_OK;
 }
 
+lbm_status lbm_batch_profile(lbm_batch *b, int64_t steps, int64_t first, int32_t count, int32_t *nwg, uint64_t *ts) {
+    if (!b || !nwg) return fail(LBM_EINVAL, "NULL argument");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
+    if (b->form == 0) return fail(LBM_EINVAL, "the step profile covers the grid forms (1 and 2) only");
+    if (steps < 1 || first < 0 || count < 1 || first + (int64_t)count > steps)
+        return fail(LBM_EINVAL, "need 0 <= first, 1 <= count, first + count <= steps");
+    lbm_status st;
+    if ((st = batch_plan(b, b->block, b->form)) != LBM_OK) return st;
+    *nwg = (int32_t)b->nwg;
+    if (!ts) return LBM_OK;
+    if ((size_t)b->nwg * (size_t)count * 3 > ((size_t)1 << 28)) return fail(LBM_EINVAL, "profile too large");
+    int32_t ab = 0;
+    if ((st = batch_profile_launch(b, steps, first, count, ts, &ab)) != LBM_OK) return st;
+    if (ab == 2) {
+        // nothing was stepped; later runs use the device-wide form
+        b->nxcd = -1;
+        if ((st = lbm_batch_set_form(b, 1, b->block)) != LBM_OK) return st;
+        return fail(LBM_EDEVICE, "workgroups did not land on the XCDs as planned: batch switched to form 1");
+    }
+    if (ab) {
+        b->poisoned = true;
+        return fail(LBM_EDEVICE, "batch grid barrier timed out: the state is undefined until lbm_batch_reset");
+    }
+    if (steps & 1)
+        for (auto &c : b->cur) c ^= 1;
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_populations(lbm_batch *b, int32_t index, double *f) {
     if (!b || !f) return fail(LBM_EINVAL, "NULL argument");
     if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
@@ -1470,15 +1505,37 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int saved_form = b->form, saved_block = b->block;
     int best_form = b->form, best_block = b->block;
     float best_ms = 1e30f;
     lbm_status st = LBM_OK;
+    // time `steps` steps of the current plan in (form, blk) after a one-step warm-up; *ms < 0 if
+    // the launch did not complete as planned
+    auto time_trial = [&](int form, int blk, float *ms) {
+        *ms = -1.0f;
+        const BatchArgs a1 = batch_args(b, 1, 0, 0, 1), an = batch_args(b, steps, 0, 0, 1);
+        e = launch_batch((int)b->storage, form, blk, a1, (uint32_t)b->count, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = launch_batch((int)b->storage, form, blk, an, (uint32_t)b->count, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        int32_t ab = 0;
+        if (e == hipSuccess && form >= 1) {
+            e = hipMemcpy(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && ab == 2) b->nxcd = -1;
+        }
+        if (e == hipSuccess && !ab) *ms = t;
+    };
     for (int form : {0, 1, 2}) {
         for (int blk : {1024, 512, 256}) {
             if (e != hipSuccess || st != LBM_OK) break;
             if (form >= 1) {
                 if (batch_grid_resident_per_cu((int)b->storage, form, blk) < 1) continue;
                 if (form == 2 && b->nxcd < 0) continue;
+                b->cal.erase({form, blk});
+                b->plan_block = 0;
                 if ((st = batch_plan(b, blk, form)) != LBM_OK) {
                     if (form == 2 && b->nxcd < 0) {   // XCD-local form unusable here: skip it
                         st = LBM_OK;
@@ -1487,29 +1544,35 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
                     break;
                 }
             }
-            const int saved_form = b->form;
             b->form = form;
-            const BatchArgs a1 = batch_args(b, 1, 0, 0, 1), an = batch_args(b, steps, 0, 0, 1);
-            b->form = saved_form;
-            e = launch_batch((int)b->storage, form, blk, a1, (uint32_t)b->count, b->stream);   // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            if (e == hipSuccess) e = launch_batch((int)b->storage, form, blk, an, (uint32_t)b->count, b->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            b->block = blk;
             float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            int32_t ab = 0;
-            if (e == hipSuccess && form >= 1) {
-                e = hipMemcpy(&ab, b->d_abort, sizeof(int32_t), hipMemcpyDeviceToHost);
-                if (e == hipSuccess && ab == 2) b->nxcd = -1;
+            time_trial(form, blk, &ms);
+            if (e == hipSuccess && form >= 1 && ms >= 0) {
+                // calibrate the plan's cost model to a step profile of this form, and keep the
+                // calibrated plan if it runs faster
+                bool ok = false;
+                if ((st = batch_calibrate(b, steps, &ok)) != LBM_OK) break;
+                if (ok) {
+                    float ms_cal = 0;
+                    time_trial(form, blk, &ms_cal);
+                    if (e == hipSuccess && ms_cal >= 0 && ms_cal < ms) {
+                        ms = ms_cal;
+                    } else {
+                        b->cal.erase({form, blk});
+                        b->plan_block = 0;
+                    }
+                }
             }
-            if (e == hipSuccess && !ab && ms < best_ms) {
+            if (e == hipSuccess && ms >= 0 && ms < best_ms) {
                 best_ms = ms;
                 best_form = form;
                 best_block = blk;
             }
         }
     }
+    b->form = saved_form;
+    b->block = saved_block;
     if (e == hipSuccess) e = hipMemcpyAsync(b->pool, save, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e0) (void)hipEventDestroy(e0);
@@ -1520,10 +1583,44 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *form, int32_
     batch_drop_graph(b);
     b->form = best_form;
     b->block = best_block;
+    b->plan_block = 0;
     if (b->form >= 1 && (st = batch_plan(b, b->block, b->form)) != LBM_OK) return st;
     if (form) *form = best_form;
     if (block) *block = best_block;
     if (ms_per_step) *ms_per_step = (double)best_ms / steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_calibrate(lbm_batch *b, int32_t steps, double *costs, int32_t *ncosts) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LBM_ESTATE, "a barrier wait expired in an earlier run: call lbm_batch_reset");
+    if (b->form == 0) return fail(LBM_EINVAL, "the cost model plans the grid forms (1 and 2) only");
+    if (steps < 0) return fail(LBM_EINVAL, "steps must be >= 0");
+    if (ncosts) *ncosts = b->nkinds + 1;
+    b->cal.erase({b->form, b->block});
+    b->plan_block = 0;
+    lbm_status st = batch_plan(b, b->block, b->form);
+    if (st != LBM_OK || steps == 0) {
+        if (st == LBM_OK && costs)
+            for (int k = 0; k <= b->nkinds; ++k) costs[k] = 0.0;
+        return st;
+    }
+    void *save = nullptr;
+    HIP_TRY(hipMalloc(&save, b->pool_bytes));
+    hipError_t e = hipMemcpyAsync(save, b->pool, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    bool ok = false;
+    if (e == hipSuccess) st = batch_calibrate(b, steps, &ok);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->pool, save, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(save);
+    HIP_TRY(e);
+    if (st != LBM_OK) return st;
+    if (!ok) return fail(LBM_EDEVICE, "step profile failed or fitted no cost: the default model stays");
+    if (costs) {
+        const std::vector<double> &c = b->cal[{b->form, b->block}];
+        for (int k = 0; k <= b->nkinds; ++k) costs[k] = c[k];
+    }
     return LBM_OK;
 }
 

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 from pathlib import Path
 
 import numpy as np
@@ -98,6 +99,10 @@ SIGNATURES = {
     "lbm_batch_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_plan_xcds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "lbm_batch_set_spin_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "lbm_autotune_cached": (ctypes.c_int, [_SIM, ctypes.c_char_p, ctypes.c_int32, _I32, _D, _I32]),
+    "lbm_batch_calibrate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "lbm_batch_sizes": (ctypes.c_int, [ctypes.c_void_p, _I64, _I64]),
     "lbm_batch_free": (None, [ctypes.c_void_p]),
     "lbm_gauss_hermite": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
@@ -343,6 +348,14 @@ class Sim:
         _check(_lib.lbm_autotune(self._h, steps_per_trial, ctypes.byref(t), ctypes.byref(ms)))
         return t.value, ms.value
 
+    def autotune_cached(self, path, steps_per_trial: int = 5):
+        """(tile, ms per step, hit): the cached choice for this configuration, else a fresh tuning
+        that is stored in the cache file `path`."""
+        t, ms, hit = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+        _check(_lib.lbm_autotune_cached(self._h, os.fsencode(os.fspath(path)), steps_per_trial, ctypes.byref(t),
+                                        ctypes.byref(ms), ctypes.byref(hit)))
+        return t.value, ms.value, bool(hit.value)
+
 
 class Batch:
     """Owner of one lbm_batch*: many shear-wave instances advanced in one persistent launch.
@@ -416,6 +429,25 @@ class Batch:
     def set_spin_limit(self, limit: int):
         """Testing hook: bound of every barrier wait in sleeps (0 = default)."""
         _check(_lib.lbm_batch_set_spin_limit(self._h, limit))
+
+    def profile(self, steps: int, first: int, count: int) -> np.ndarray:
+        """Advance `steps` steps in a grid form with per-workgroup timestamps (100 MHz ticks) of
+        steps first .. first + count - 1: ts[w, k] = (start, chunks done, barrier passed)."""
+        n = ctypes.c_int32()
+        _check(_lib.lbm_batch_profile(self._h, steps, first, count, ctypes.byref(n), None))
+        ts = np.zeros((n.value, count, 3), np.uint64)
+        _check(_lib.lbm_batch_profile(self._h, steps, first, count, ctypes.byref(n),
+                                      ts.ctypes.data_as(ctypes.c_void_p)))
+        return ts
+
+    def calibrate(self, steps: int) -> np.ndarray:
+        """Fit the grid plan's cost model to a step profile of `steps` steps (0: back to the
+        default model); returns the per-cell costs of each velocity set present, then the
+        per-chunk cost.  The state is unchanged."""
+        c = np.zeros(8)
+        n = ctypes.c_int32()
+        _check(_lib.lbm_batch_calibrate(self._h, steps, _dp(c), ctypes.byref(n)))
+        return c[:n.value].copy()
 
     def form(self):
         """(form, block) in use (a run can move form 2 to form 1)."""

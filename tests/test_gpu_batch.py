@@ -235,3 +235,72 @@ def test_barrier_timeout_leaves_state_undefined_until_reset(form):
         assert np.array_equal(amp_a, amp_b)
         for i in (0, 100, 255):
             assert np.array_equal(a.populations(i), b.populations(i))
+
+
+@pytest.mark.parametrize("form,block", [(1, 512), (2, 256)])
+def test_step_profile_steps_like_a_run_and_orders_its_timestamps(form, block):
+    """lbm_batch_profile advances the batch exactly as lbm_batch_run does (same populations,
+    bit for bit, an odd step count included), and each workgroup's timestamps are ordered:
+    start <= chunks done <= barrier passed <= next step's start; no workgroup passes a step's
+    barrier before the last one has finished that step's chunks."""
+    lbm = need_gpu()
+    from paper_0908_4520_amd import batch_profile
+    inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, kn, nx, ny in SMALL if not math.isinf(kn)]
+    with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(form, block)
+        b.set_form(form, block)
+        ts = a.profile(37, 10, 8)
+        b.run(37, 37, record=False)
+        for i in range(len(inst)):
+            assert np.array_equal(a.populations(i), b.populations(i))
+        nwg = ts.shape[0]
+        say(f"form {form}/{block}: {nwg} workgroups, {batch_profile.split(ts)}")
+        assert nwg >= 1 and ts.shape[1:] == (8, 3)
+        t = ts.astype(np.int64)
+        assert np.all(t > 0)
+        assert np.all(np.diff(t, axis=2) >= 0)
+        assert np.all(t[:, 1:, 0] >= t[:, :-1, 2])
+        if form == 1:
+            # one device-wide barrier: every release follows every workgroup's work (the clock
+            # is read on different XCDs; allow 1 us of skew)
+            margin = t[:, :, 2].min(axis=0) - t[:, :, 1].max(axis=0)
+            say(f"least release after the last arrival: {margin.min() * 10} ns")
+            assert np.all(margin >= -100)
+        for bad in ((0, 0, 1), (10, 5, 6), (10, -1, 2), (10, 0, 0)):
+            with pytest.raises(lbm.LbmError) as e:
+                a.profile(*bad)
+            assert e.value.code == lbm.LBM_EINVAL
+        a.set_form(0, 256)
+        with pytest.raises(lbm.LbmError) as e:
+            a.profile(4, 0, 2)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("form,block", [(1, 256), (2, 512)])
+def test_calibrated_plan_changes_nothing_computed(form, block):
+    """lbm_batch_calibrate fits the plan's cost model (one cost per cell for each velocity set
+    present, one per chunk, none of them zero), leaves the state alone, and the calibrated plan
+    steps every instance bit for bit like the per-instance form; steps = 0 restores the default
+    model."""
+    lbm = need_gpu()
+    inst = [(lat, N, _tau(lbm, lat, kn, ny), (nx, ny), A0) for lat, N, kn, nx, ny in SMALL if not math.isinf(kn)]
+    with lbm.Batch(inst) as a, lbm.Batch(inst) as b:
+        a.set_form(form, block)
+        b.set_form(0, 256)
+        a.run(3, 3, record=False)
+        b.run(3, 3, record=False)
+        before = [a.populations(i) for i in range(len(inst))]
+        c = a.calibrate(40)
+        say(f"form {form}/{block}: fitted costs {c}")
+        assert c.shape == (len({x[0] for x in inst}) + 1,) and np.all(c > 0)
+        for i in range(len(inst)):
+            assert np.array_equal(a.populations(i), before[i])
+        amp_a, amp_b = a.run(25, 5), b.run(25, 5)
+        assert np.array_equal(amp_a, amp_b)
+        for i in range(len(inst)):
+            assert np.array_equal(a.populations(i), b.populations(i))
+        assert np.all(a.calibrate(0) == 0)
+        a.set_form(0, 256)
+        with pytest.raises(lbm.LbmError) as e:
+            a.calibrate(10)
+        assert e.value.code == lbm.LBM_EINVAL
