@@ -1,7 +1,7 @@
 """Per-step split of the Kn-sweep batch's persistent run into chunk work and barrier wait.
 
     python -m paper_0908_4520_amd.batch_profile [--count 256] [--steps 2000] [--window 64]
-                                                [--forms 2/512,2/1024,1/512]
+                                                [--forms 2/512,2/1024,1/512] [--calibrate 500]
 
 For each (form, workgroup size) the batch is warmed up, reset, and advanced `steps` steps through
 lbm_batch_profile, which timestamps a window of steps in the middle of the run on every
@@ -48,6 +48,9 @@ def main(argv=None) -> int:
     ap.add_argument("--window", type=int, default=64)
     ap.add_argument("--forms", default="2/512,2/1024,2/256,1/512,1/1024")
     ap.add_argument("--dump", default=None, help="also write every workgroup's timestamps to this .npz file")
+    ap.add_argument("--calibrate", type=int, default=0,
+                    help="then fit the plan's cost model to a step profile of this many steps "
+                         "(lbm_batch_calibrate) and measure the calibrated plan too")
     args = ap.parse_args(argv)
 
     from . import lbm, workloads
@@ -59,19 +62,26 @@ def main(argv=None) -> int:
         for fb in args.forms.split(","):
             form, block = (int(v) for v in fb.split("/"))
             b.set_form(form, block)
-            b.run(args.steps, args.steps, record=False)     # warm-up (and graph build)
-            b.reset()
-            t0 = time.perf_counter()
-            b.run(args.steps, args.steps, record=False)     # the plain kernel, for comparison
-            run_us = (time.perf_counter() - t0) * 1e6 / args.steps
-            b.reset()
-            ts = b.profile(args.steps, first, args.window)
-            b.reset()
-            out = dict(form=form, block=block, instances=args.count, steps=args.steps,
-                       cells_per_step=b.cells, bytes_per_step=b.bytes_per_step,
-                       run_us_per_step=round(run_us, 3), **split(ts))
-            print(json.dumps(out), flush=True)
-            dumps[f"ts_{form}_{block}"] = ts
+            plans = [("default", None)] + ([("calibrated", args.calibrate)] if args.calibrate else [])
+            for plan, cal in plans:
+                costs = b.calibrate(cal) if cal else None
+                b.run(args.steps, args.steps, record=False)     # warm-up (and graph build)
+                b.reset()
+                t0 = time.perf_counter()
+                b.run(args.steps, args.steps, record=False)     # the plain kernel, for comparison
+                run_us = (time.perf_counter() - t0) * 1e6 / args.steps
+                b.reset()
+                ts = b.profile(args.steps, first, args.window)
+                b.reset()
+                out = dict(form=form, block=block, plan=plan, instances=args.count, steps=args.steps,
+                           cells_per_step=b.cells, bytes_per_step=b.bytes_per_step,
+                           run_us_per_step=round(run_us, 3), **split(ts))
+                if costs is not None:
+                    out["fitted_costs"] = [round(float(c), 4) for c in costs]
+                print(json.dumps(out), flush=True)
+                dumps[f"ts_{form}_{block}_{plan}"] = ts
+            if args.calibrate:
+                b.calibrate(0)
     if args.dump:
         np.savez_compressed(args.dump, **dumps)
     return 0

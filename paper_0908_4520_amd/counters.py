@@ -7,6 +7,10 @@ non-temporal stores), so one shape is one tile choice of one configuration.
   python -m paper_0908_4520_amd.counters trace DIR
       per-shape durations from DIR/run_kernel_trace.csv (rocprofv3 --kernel-trace)
 
+  python -m paper_0908_4520_amd.counters pmc DIR [--kernel REGEX]
+      mean of every counter of a --pmc run per launch shape (SQ counters: VALU instructions per
+      wave and per cell, the share of SIMD cycles issuing VALU work)
+
   python -m paper_0908_4520_amd.counters traffic FETCH_DIR WRITE_DIR --calib-bytes B
           [--kernel REGEX --alg-read-bytes R --tag TAG --json profiles/traffic.json]
       HBM bytes per launch from two counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE;
@@ -181,6 +185,42 @@ def cmd_traffic(args):
         print(f"\nwrote {len(shapes)} shapes of {args.tag} to {args.json}", file=sys.stderr)
 
 
+def cmd_pmc(args):
+    """Mean of every counter of a --pmc run per launch shape, for the kernels matching --kernel.
+    With --cells (cells one launch updates): VALU instructions per cell (a wave instruction
+    serves 64 cells).  VALU issue share: a wave's VALU instruction occupies its SIMD for 4
+    cycles, so SQ_INSTS_VALU x 4 / (4 SIMDs x --cus x duration x --clock-ghz) is the share of the
+    SIMDs' cycles spent issuing VALU work (at the nominal clock; a lower clock under load raises
+    it)."""
+    rows = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    with open(os.path.join(args.dir, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if args.kernel and not re.search(args.kernel, r["Kernel_Name"]):
+                continue
+            wg, grid = int(r["Workgroup_Size"]), int(r["Grid_Size"])
+            if grid // wg < args.min_wgs:
+                continue
+            key = (r["Kernel_Name"], wg, grid // wg)
+            rows[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            dur[key][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    names = sorted({c for v in rows.values() for c in v})
+    print("| kernel | threads/WG | WGs | dispatches | duration (us) | " + " | ".join(names) +
+          " | VALU instr. per wave | VALU instr. per cell | VALU issue share |")
+    print("|---|---:|---:|---:|---:|" + "---:|" * len(names) + "---:|---:|---:|")
+    for key, cs in sorted(rows.items()):
+        name, wg, nwg = key
+        mean = {c: sum(v) / len(v) for c, v in cs.items()}
+        us = sum(dur[key].values()) / len(dur[key]) / 1e3
+        waves = mean.get("SQ_WAVES", 0.0)
+        valu = mean.get("SQ_INSTS_VALU", 0.0)
+        per_wave = f"{valu / waves:.0f}" if waves else "--"
+        per_cell = f"{valu * 64 / args.cells:.0f}" if args.cells and valu else "--"
+        share = f"{valu * 4 / (4 * args.cus * us * 1e3 * args.clock_ghz):.2f}" if valu and us > 0 else "--"
+        print(f"| `{name}` | {wg} | {nwg} | {len(dur[key])} | {us:.1f} | " +
+              " | ".join(f"{mean.get(c, float('nan')):.4g}" for c in names) + f" | {per_wave} | {per_cell} | {share} |")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -197,9 +237,18 @@ def main(argv=None):
     c.add_argument("--tag", default=None)
     c.add_argument("--json", default=None)
     c.add_argument("--min-bytes", type=float, default=1e6, help="omit launches that move fewer bytes")
+    q = sub.add_parser("pmc")
+    q.add_argument("dir")
+    q.add_argument("--kernel", default=None)
+    q.add_argument("--cells", type=int, default=0, help="cells one launch updates (for the per-cell column)")
+    q.add_argument("--cus", type=int, default=256)
+    q.add_argument("--clock-ghz", type=float, default=2.4)
+    q.add_argument("--min-wgs", type=int, default=0, help="omit launches of fewer workgroups")
     args = ap.parse_args(argv)
     if args.cmd == "trace":
         cmd_trace(args)
+    elif args.cmd == "pmc":
+        cmd_pmc(args)
     else:
         if args.json and not (args.tag and args.kernel):
             ap.error("--json needs --tag and --kernel")

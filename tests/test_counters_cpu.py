@@ -77,3 +77,22 @@ def test_calibration_needs_the_copy(tmp_path):
     _pmc(wd, "WRITE_SIZE", [(K512, 512, 512 * 8192, 1.0)])
     with pytest.raises(SystemExit):
         counters.calibration(counters.read_counter(fd, "FETCH_SIZE"), counters.read_counter(wd, "WRITE_SIZE"), 4096)
+
+
+def test_batch_profile_split_of_synthetic_timestamps():
+    """The step split reads start / chunks-done / released ticks (10 ns) per workgroup and step."""
+    import numpy as np
+    from paper_0908_4520_amd.batch_profile import split
+    # two workgroups, three steps of 20 us; workgroup 0 works 15 us, workgroup 1 works 19 us
+    ts = np.zeros((2, 3, 3), np.uint64)
+    for k in range(3):
+        t0 = 1000 + 2000 * k
+        ts[0, k] = (t0, t0 + 1500, t0 + 1950)
+        ts[1, k] = (t0 + 10, t0 + 1910, t0 + 1960)
+    s = split(ts)
+    assert s["nwg"] == 2 and s["steps_profiled"] == 3
+    assert s["step_us_median"] == 20.0
+    assert s["work_us_busiest_wg"] == 19.0
+    assert abs(s["work_us_mean"] - 17.0) < 1e-12
+    assert abs(s["wait_us_mean"] - (4.5 + 0.5) / 2) < 1e-12
+    assert s["wait_us_least"] == 0.5
