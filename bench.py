@@ -212,6 +212,11 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
                    bytes_per_step=s.bytes_per_step, ncell=s.ncell, buffers="torch (lbm_opts.dev_buf)")
     del bufs
     torch.cuda.empty_cache()
+    if nbytes >= (64 << 20):
+        # the practical ceiling for these bytes: the library's copy of one state buffer (read once,
+        # written once, the same bytes per step as the step kernel)
+        cg, _, cb = copy_ceiling(lbm, torch, stream, nbytes)
+        res.update(copy_gbs_same_size=round(cg, 1), copy_blocks=cb, frac_of_same_size_copy=round(gbs / cg, 4))
     return res
 
 
