@@ -50,8 +50,8 @@ def shape_key(block: int, blocks: int, nontemporal: bool, vector: int = 1, extra
 
 
 def _bw_extra(name: str) -> str:
-    """k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL>: alternating strip walks and non-temporal loads,
-    which the launch shape alone does not tell apart."""
+    """k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL, PIPE>: alternating strip walks, non-temporal loads
+    and the software-pipelined walk, which the launch shape alone does not tell apart."""
     if "k_bw2<" not in name:
         return ""
     args = _template_args(name)
@@ -60,6 +60,8 @@ def _bw_extra(name: str) -> str:
         out += ":alt"
     if len(args) >= 9 and args[8] == "true":
         out += ":ntl"
+    if len(args) >= 10 and args[9] == "true":
+        out += ":pipe"
     return out
 
 

@@ -18,9 +18,9 @@ namespace host {
 const ShiftTile kShiftTiles[kShiftTileCount] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 256, 8},
                                                 {2, 512, 4}, {2, 512, 2}, {2, 512, 1}, {1, 256, 4},
                                                 {1, 256, 8}, {3, 256, 1}, {3, 256, 2}};
-const BWTile kBWTiles[kBWTileCount] = {{16, 0}, {32, 0}, {8, 0},  {4, 0},  {64, 0}, {16, 1},
-                                       {32, 1}, {8, 1},  {16, 2}, {32, 2}, {8, 2},  {4, 2},
-                                       {64, 2}, {10, 2}, {12, 2}, {13, 2}, {8, 3},  {16, 3}};
+const BWTile kBWTiles[kBWTileCount] = {{16, 0}, {32, 0}, {8, 0},  {4, 0},  {64, 0}, {16, 1}, {32, 1}, {8, 1},
+                                       {16, 2}, {32, 2}, {8, 2},  {4, 2},  {64, 2}, {10, 2}, {12, 2}, {13, 2},
+                                       {8, 3},  {16, 3}, {8, 4},  {16, 4}, {4, 4},  {32, 4}};
 
 namespace {
 

@@ -23,7 +23,8 @@ struct ShiftTile {
 };
 // Beam-Warming tiles: rows per strip and variant (0: plain stores, 1: non-temporal stores,
 // 2: non-temporal stores and alternating walk directions of neighbouring strips, 3: variant 2
-// with non-temporal loads of the stencil's own column).
+// with non-temporal loads of the stencil's own column, 4: variant 2 with the next row's loads
+// issued before the current row is computed).
 struct BWTile {
     int rows, variant;
 };
@@ -32,7 +33,7 @@ extern const BWTile kBWTiles[];
 constexpr int kShiftTileCount = 11;
 constexpr int kPlainShiftTiles = 9;    // without the vector tiles (variant 3)
 constexpr int kForcedShiftTiles = 7;   // the forced row kernel exists as variants 0 and 2 only
-constexpr int kBWTileCount = 18;
+constexpr int kBWTileCount = 22;
 constexpr int kForcedBWTiles = 5;      // the forced Beam-Warming kernel exists as variant 0 only
 
 // What the tile choice depends on.

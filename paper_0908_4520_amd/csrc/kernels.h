@@ -117,10 +117,11 @@ struct KernelSet {
     StepFn shift_rows4;    // on-lattice shift, 4 cells per thread, vector loads and stores, non-temporal
                            // loads (FP32 storages, |c_x| <= 4, nx a multiple of 256; else null)
     StepFn shift_cells;    // on-lattice shift, one thread per cell (any grid)
-    StepBW32 bw2_f32[4];   // Beam-Warming advection (2-D sets), FP32 collision: plain stores,
+    StepBW32 bw2_f32[5];   // Beam-Warming advection (2-D sets), FP32 collision: plain stores,
                            // non-temporal stores, non-temporal stores with alternating strip walks,
-                           // the same with non-temporal loads
-    StepBW64 bw2_f64[4];   // the same with the FP64 collision
+                           // the same with non-temporal loads, the same (plain loads) with the next
+                           // row's loads issued before the current row is computed
+    StepBW64 bw2_f64[5];   // the same with the FP64 collision
     // The same with the body force (row tiles: 256 threads with plain stores, 512 threads with
     // non-temporal stores)
     StepFn shift_rows_forced[2];

@@ -386,7 +386,7 @@ constexpr int bw_slot(int i, int d) {
     return i;
 }
 
-template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false>
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false, bool PIPE = false>
 __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     static_assert(L::D == 2, "Beam-Warming kernel is two-dimensional");
     using C = Codec<S>;
@@ -418,22 +418,28 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
     const uint32_t ps = (uint32_t)a.lay.pop * es, rowb = (uint32_t)a.lay.row * es;
     const uint32_t xlb = (uint32_t)xl * es, hlb = (uint32_t)hl * es, hrb = (uint32_t)hr * es, xob = (uint32_t)xo * es;
     auto row_of = [&](int r) { return (size_t)wrap_once(wrap_once(r, ny), ny) * rowb; };
-    auto xadv = [&](auto I, size_t roff) -> T {
+    // x-advected value of population i from its column's raw value and its halo column's
+    auto xadv_raw = [&](auto I, raw f0r, raw hr) -> T {
         constexpr int i = decltype(I)::value;
         constexpr int kx = bw_slot<L>(i, 0);
-        const __amdgpu_buffer_rsrc_t rr = make_rsrc(fin + roff, rowb);
-        const T f0 = (T)C::dec(buf_load<raw, NTL>(rr, xlb, (uint32_t)i * ps));
+        const T f0 = (T)C::dec(f0r), h = (T)C::dec(hr);
         T f1, f2;
         if constexpr (L::xi[i][0] > 0.0) {            // upwind = left: f(x-1), f(x-2)
-            const T h = (T)C::dec(buf_load<raw>(rr, hlb, (uint32_t)i * ps));
             f1 = dpp_shr(h, f0);
             f2 = dpp_shr(dpp_shl(h, h), f1);
         } else {                                      // upwind = right: f(x+1), f(x+2)
-            const T h = (T)C::dec(buf_load<raw>(rr, hrb, (uint32_t)i * ps));
             f1 = dpp_shl(h, f0);
             f2 = dpp_shl(dpp_shr(h, h), f1);
         }
         return f0 - cf.alpha[0][kx] * (f0 - f1) + cf.beta[0][kx] * (f1 - f2);
+    };
+    constexpr auto halo_of = [](int i) { return L::xi[i][0] > 0.0; };   // true: the halo is on the left
+    auto xadv = [&](auto I, size_t roff) -> T {
+        constexpr int i = decltype(I)::value;
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(fin + roff, rowb);
+        const raw f0r = buf_load<raw, NTL>(rr, xlb, (uint32_t)i * ps);
+        const raw hr = buf_load<raw>(rr, halo_of(i) ? hlb : hrb, (uint32_t)i * ps);
+        return xadv_raw(I, f0r, hr);
     };
     const T om = (T)a.omega;
     double ss = 0.0, sc = 0.0;
@@ -453,26 +459,23 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
                 B[i] = xadv(I, row_of(ys - D));
             }
         });
-        for (int k = 0; k < y1 - y0; ++k) {
-            const int y = ys + D * k;
-            T v[L::Q];
-            const size_t r0 = row_of(y), r2 = row_of(y + 2 * D);
-            static_for<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                constexpr int ky = bw_slot<L>(i, 1);
-                constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
-                if constexpr (along) {             // A = row y, B = row y+D, new row y+2D
-                    const T Cn = xadv(I, r2);
-                    v[i] = A[i] - cf.alpha[1][ky] * (A[i] - B[i]) + cf.beta[1][ky] * (B[i] - Cn);
-                    A[i] = B[i];
-                    B[i] = Cn;
-                } else {                           // A = row y-2D, B = row y-D, new row y
-                    const T Cn = xadv(I, r0);
-                    v[i] = Cn - cf.alpha[1][ky] * (Cn - B[i]) + cf.beta[1][ky] * (B[i] - A[i]);
-                    A[i] = B[i];
-                    B[i] = Cn;
-                }
-            });
+        // y-advection of population i with the window (A, B) and the new row's x-advected value
+        auto yadv = [&](auto I, T Cn) -> T {
+            constexpr int i = decltype(I)::value;
+            constexpr int ky = bw_slot<L>(i, 1);
+            constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
+            T out;
+            if constexpr (along)                   // A = row y, B = row y+D, new row y+2D
+                out = A[i] - cf.alpha[1][ky] * (A[i] - B[i]) + cf.beta[1][ky] * (B[i] - Cn);
+            else                                   // A = row y-2D, B = row y-D, new row y
+                out = Cn - cf.alpha[1][ky] * (Cn - B[i]) + cf.beta[1][ky] * (B[i] - A[i]);
+            A[i] = B[i];
+            B[i] = Cn;
+            return out;
+        };
+        // collision and store of row y
+        auto finish = [&](int y, T (&v)[L::Q]) {
+            const size_t r0 = row_of(y);
             if constexpr (F) {
                 T sig[2];
                 collide_impl<L, N, S, T, true>(v, om, (T)(a.force_g * a.force_cos[y]), sig);
@@ -492,6 +495,53 @@ __global__ __launch_bounds__(kBlock) void k_bw2(StepArgs a, BWCoef<T> cf) {
                     const raw r = C::template enc<SR>(v[i], SR ? pop_bits<i>(hb) : 0u);
                     buf_store<NTS>(r, wr, xob, (uint32_t)i * ps);
                 });
+            }
+        };
+        const int n = y1 - y0;
+        if constexpr (!PIPE) {
+            for (int k = 0; k < n; ++k) {
+                const int y = ys + D * k;
+                T v[L::Q];
+                const size_t r0 = row_of(y), r2 = row_of(y + 2 * D);
+                static_for<L::Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
+                    v[i] = yadv(I, xadv(I, along ? r2 : r0));
+                });
+                finish(y, v);
+            }
+        } else {
+            // software pipeline: the loads of row k + 1 are issued before row k is computed, so
+            // a wave's next loads are in flight while it computes (one row of raw values more
+            // in registers)
+            raw fn[L::Q], hn[L::Q];
+            auto prefetch = [&](int k) {
+                const int y = ys + D * k;
+                const size_t r0 = row_of(y), r2 = row_of(y + 2 * D);
+                static_for<L::Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    constexpr bool along = (L::xi[i][1] < 0.0) == (D > 0);
+                    const __amdgpu_buffer_rsrc_t rr = make_rsrc(fin + (along ? r2 : r0), rowb);
+                    fn[i] = buf_load<raw, NTL>(rr, xlb, (uint32_t)i * ps);
+                    hn[i] = buf_load<raw>(rr, halo_of(i) ? hlb : hrb, (uint32_t)i * ps);
+                });
+            };
+            prefetch(0);
+            for (int k = 0; k < n; ++k) {
+                raw fc[L::Q], hc[L::Q];
+                static_for<L::Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    fc[i] = fn[i];
+                    hc[i] = hn[i];
+                });
+                if (k + 1 < n) prefetch(k + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                T v[L::Q];
+                static_for<L::Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    v[i] = yadv(I, xadv_raw(I, fc[i], hc[i]));
+                });
+                finish(ys + D * k, v);
             }
         }
     };
@@ -689,9 +739,9 @@ hipError_t launch_shift_cells(const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_shift_cells<L, N, S, SR, F>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
-template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false>
+template <class L, int N, int S, bool SR, class T, bool F, bool NTS, bool ALT, bool NTL = false, bool PIPE = false>
 hipError_t launch_bw2(const StepArgs &a, const BWCoef<T> &cf, hipStream_t s) {
-    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
+    hipLaunchKernelGGL((k_bw2<L, N, S, SR, T, F, NTS, ALT, NTL, PIPE>), dim3(a.nblocks), dim3(kBlock), 0, s, a, cf);
     return hipGetLastError();
 }
 template <class L, int N, int S>
@@ -768,12 +818,14 @@ KernelSet make_set() {
             k.bw2_f64[1] = &launch_bw2<L, N, S, SR, double, false, true, false>;
             k.bw2_f64[2] = &launch_bw2<L, N, S, SR, double, false, true, true>;
             k.bw2_f64[3] = &launch_bw2<L, N, S, SR, double, false, true, true, true>;
+            k.bw2_f64[4] = &launch_bw2<L, N, S, SR, double, false, true, true, false, true>;
             k.bw2_f64_forced = &launch_bw2<L, N, S, SR, double, true, false, false>;
         } else {
             k.bw2_f32[0] = &launch_bw2<L, N, S, SR, float, false, false, false>;
             k.bw2_f32[1] = &launch_bw2<L, N, S, SR, float, false, true, false>;
             k.bw2_f32[2] = &launch_bw2<L, N, S, SR, float, false, true, true>;
             k.bw2_f32[3] = &launch_bw2<L, N, S, SR, float, false, true, true, true>;
+            k.bw2_f32[4] = &launch_bw2<L, N, S, SR, float, false, true, true, false, true>;
             k.bw2_f32_forced = &launch_bw2<L, N, S, SR, float, true, false, false>;
         }
     }

@@ -49,7 +49,7 @@ def test_library_loads_and_reports_sizes():
             per_row, cover = i["blocks"] // 17, i["block"] * i["cells_per_thread"]
             assert i["blocks"] % 17 == 0 and per_row * cover >= 300 and (per_row - 1) * cover < 300
     with lbm.Sim("D2Q16-GH", 3, 3.0, (300, 17, 1), storage="fp32_dev") as s:
-        assert s.tile_count() == 18
+        assert s.tile_count() == 22
         for t in range(s.tile_count()):
             i = s.tile_info(t)
             assert i["block"] == 256 and i["nontemporal"] == (t >= 5)
