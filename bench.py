@@ -223,17 +223,20 @@ def run_variant(lbm, torch, stream, lattice, N, kn, grid, storage, axis, steps, 
 def copy_ceiling(lbm, torch, stream, nbytes, reps=10):
     """Read+write bandwidth of the library's grid-stride 16-byte copy (lbm_device_copy) of nbytes,
     best over a few grid sizes: the practical HBM ceiling for a kernel that reads and writes each
-    byte once."""
+    byte once.  The copies go back and forth between two buffers, as a time step does between its
+    two state buffers (copying one way again and again would read a source that stays in the
+    Infinity Cache when it is small)."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
+    bufs = (src.data_ptr(), dst.data_ptr())
     best = None
     for blocks in (1024, 2048, 4096, 16384):
         lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, blocks, stream.cuda_stream)
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         s.record(stream)
-        for _ in range(reps):
-            lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, blocks, stream.cuda_stream)
+        for r in range(reps):
+            lbm.lbm_device_copy(bufs[(r + 1) & 1], bufs[r & 1], nbytes, blocks, stream.cuda_stream)
         e.record(stream)
         torch.cuda.synchronize()
         ms = s.elapsed_time(e) / reps
