@@ -161,6 +161,12 @@ __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             v[i] = C::dec(rv[i]);
+            // FP16: keep only the decoded FP32 value live.  Otherwise the compiler folds the
+            // conversion into mixed-precision FMAs that read the half value, and both forms of
+            // every population stay in registers through the collision (159 registers, 3 waves
+            // per SIMD, against 126 for BF16; the forced kernels keep the folding, which suits
+            // their register allocation better).  The empty statement emits no instruction.
+            if constexpr (S == ST_FP16_DEV && !F) asm volatile("" : "+v"(v[i]));
         });
         if constexpr (F) {
             T sig[2];
