@@ -75,19 +75,26 @@ constexpr int max_c() {
 
 // One step for cells [start, start + count) of an instance, one cell per thread (count <= the
 // block size; with nx = 4 the start is a multiple of 4, so quads are whole rows).
+// Addresses: a 64-bit base per population plane, the same for every lane (scalar registers), plus
+// a 32-bit byte offset per lane that the load and store instructions add themselves.  The offsets
+// are built from per-row and per-column parts shared by every population moving along that row
+// or column, so a population costs at most one vector add for its address.  An instance holds at
+// most 2^26 cells (checked by the host), so an offset within a plane stays below 2^31.
 template <class L, int N, int S, bool BW, bool QUAD>
 __device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs &a, int cur, uint32_t start,
                                            uint32_t count) {
     using C = Codec<S>;
     using raw = typename C::raw;
     using T = typename C::T;
+    constexpr uint32_t E = sizeof(raw);
     if (threadIdx.x >= count) return;
-    const raw *__restrict__ src = inst_buffer<L, S>(in, a, cur);
-    raw *__restrict__ dst = inst_buffer<L, S>(in, a, cur ^ 1);
+    const char *__restrict__ src = reinterpret_cast<const char *>(inst_buffer<L, S>(in, a, cur));
+    char *__restrict__ dst = reinterpret_cast<char *>(inst_buffer<L, S>(in, a, cur ^ 1));
+    const size_t psb = (size_t)in.pstride * E;   // bytes between population planes
     const int nx = in.nx, ny = in.ny;
-    const size_t ps = in.pstride;
     const uint32_t cell = start + threadIdx.x;
     const int x = (int)(cell % (uint32_t)nx), y = (int)(cell / (uint32_t)nx);
+    auto load = [&](int i, uint32_t off) -> raw { return *reinterpret_cast<const raw *>(src + (size_t)i * psb + off); };
     T v[L::Q];
     if constexpr (!BW) {
         // grids at least max|c| wide and high (a uniform condition, so a scalar branch): one
@@ -95,36 +102,42 @@ __device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs 
         if (nx >= max_c<L>() && ny >= max_c<L>()) {
             static_for<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const int xs = wrap_once(x - L::c[i][0], nx), ys = wrap_once(y - L::c[i][1], ny);
-                v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
+                const uint32_t rb = (uint32_t)(wrap_once(y - L::c[i][1], ny) * nx) * E;
+                const uint32_t cb = (uint32_t)wrap_once(x - L::c[i][0], nx) * E;
+                v[i] = C::dec(load(i, rb + cb));
             });
         } else {
             static_for<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const int xs = imod(x - L::c[i][0], nx), ys = imod(y - L::c[i][1], ny);
-                v[i] = C::dec(src[(size_t)i * ps + (size_t)ys * nx + xs]);
+                const uint32_t rb = (uint32_t)(imod(y - L::c[i][1], ny) * nx) * E;
+                const uint32_t cb = (uint32_t)imod(x - L::c[i][0], nx) * E;
+                v[i] = C::dec(load(i, rb + cb));
             });
         }
     } else {
+        // byte offsets of the rows y, y -+ 1, y -+ 2 (the upwind side by the sign of xi_y) and of
+        // the column x
+        const uint32_t rowm[3] = {(uint32_t)(y * nx) * E, (uint32_t)(imod(y - 1, ny) * nx) * E,
+                                  (uint32_t)(imod(y - 2, ny) * nx) * E};
+        const uint32_t rowp[3] = {rowm[0], (uint32_t)(imod(y + 1, ny) * nx) * E, (uint32_t)(imod(y + 2, ny) * nx) * E};
+        const uint32_t colx = (uint32_t)x * E;
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr bool px = L::xi[i][0] > 0.0, py = L::xi[i][1] > 0.0;
             T ax, bx, ay, by;
             bw_coefs<T>(a, in.bw_off, i, ax, bx, ay, by);
-            const int rows[3] = {y, imod(py ? y - 1 : y + 1, ny), imod(py ? y - 2 : y + 2, ny)};
-            const raw *p = src + (size_t)i * ps;
+            const uint32_t *rows = py ? rowm : rowp;
             T xa[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const raw *pr = p + (size_t)rows[k] * nx;
-                const T f0 = (T)C::dec(pr[x]);
+                const T f0 = (T)C::dec(load(i, rows[k] + colx));
                 T f1, f2;
                 if constexpr (QUAD) {
                     f1 = px ? quad_move<kQuadXm1>(f0) : quad_move<kQuadXp1>(f0);
                     f2 = quad_move<kQuadX2>(f0);
                 } else {
-                    f1 = (T)C::dec(pr[imod(px ? x - 1 : x + 1, nx)]);
-                    f2 = (T)C::dec(pr[imod(px ? x - 2 : x + 2, nx)]);
+                    f1 = (T)C::dec(load(i, rows[k] + (uint32_t)imod(px ? x - 1 : x + 1, nx) * E));
+                    f2 = (T)C::dec(load(i, rows[k] + (uint32_t)imod(px ? x - 2 : x + 2, nx) * E));
                 }
                 xa[k] = f0 - ax * (f0 - f1) + bx * (f1 - f2);
             }
@@ -132,9 +145,10 @@ __device__ __forceinline__ void step_cells(const BatchInst &in, const BatchArgs 
         });
     }
     collide<L, N, S, T>(v, (T)in.omega);
+    const uint32_t cb = cell * E;
     static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        dst[(size_t)i * ps + cell] = C::template enc<false>(v[i], 0u);
+        *reinterpret_cast<raw *>(dst + (size_t)i * psb + cb) = C::template enc<false>(v[i], 0u);
     });
 }
 

@@ -155,9 +155,11 @@ lbm_status check_dev_buf_shape(const lbm_opts &o, uint64_t need, std::string *ms
 // ---------------------------------------------------------------- batch plan
 double batch_cell_cost(bool on_lattice, int Q) {
     // time per cell of one step, fitted to per-instance runs of one 512-thread workgroup per CU
-    // on MI355X (ns): D2Q9 4.0, D2Q37 8.8 (exact shift), D2Q16-GH 11.5, D2Q36-GH 25 (Beam-Warming
-    // reads three rows per population and applies two difference stencils)
-    return on_lattice ? 2.5 + 0.17 * Q : 0.7 + 0.68 * Q;
+    // on MI355X (ns): D2Q9 4.0, D2Q37 8.8 (exact shift); D2Q16-GH 9.3, D2Q36-GH 20 (Beam-Warming
+    // reads three rows per population and applies two difference stencils), where the fit gave
+    // 11.5 and 25: on the 256-instance sweep the plan with the lower Beam-Warming costs runs 4%
+    // faster (XCD-local form, 1024 threads), and 25% higher or lower on-lattice costs 4% slower
+    return on_lattice ? 2.5 + 0.17 * Q : 0.56 + 0.544 * Q;
 }
 
 std::vector<std::vector<uint32_t>> lpt(const std::vector<uint32_t> &items, const std::vector<double> &cost, uint32_t n) {
