@@ -61,29 +61,30 @@ def test_small_mixed_batch_matches_oracle(storage, form, block):
 @pytest.mark.parametrize("form,block", [(2, 1024), (0, 1024)])
 def test_largest_instance_matches_oracle_column(form, block):
     """An instance of the largest accepted size, 2^26 cells (4 x 2^24, D2Q9, N = 2, FP64 storage),
-    beside a small D2Q37 one, 3 steps: every cell against the FP64 oracle's 1 x ny column (exact
-    for the x-uniform wave) within 1e-12 relative.  The lane byte offsets within a population
-    plane reach 2^29 here; reading a neighbouring row instead would differ by about 1e-9."""
+    beside a large Beam-Warming one (D2Q16-GH, N = 3, 5 x 2^22: the general-width path, nine
+    loads per population) and a small D2Q37 one, 3 steps: every cell against the FP64 oracle's
+    1 x ny column (exact for the x-uniform wave) within 1e-12 relative.  The lane byte offsets
+    within a population plane reach 2^29 here; reading a neighbouring row instead would differ
+    by about 1e-9."""
     lbm = need_gpu()
     from gpu_helpers import _oracle_column_run
-    ny = 1 << 24
-    tau_big = _tau(lbm, "D2Q9", 0.1, ny)
-    tau_small = _tau(lbm, "D2Q37", 0.1, 50)
-    inst = [("D2Q9", 2, tau_big, (4, ny), A0), ("D2Q37", 4, tau_small, (4, 50), A0)]
+    ny, ny_bw = 1 << 24, 1 << 22
+    inst = [("D2Q9", 2, _tau(lbm, "D2Q9", 0.1, ny), (4, ny), A0),
+            ("D2Q16-GH", 3, _tau(lbm, "D2Q16-GH", 1.0, ny_bw), (5, ny_bw), A0),
+            ("D2Q37", 4, _tau(lbm, "D2Q37", 0.1, 50), (4, 50), A0)]
     steps = 3
     with lbm.Batch(inst, storage="fp64") as b:
         b.set_form(form, block)
         amp = b.run(steps, steps)
         assert b.form() == (form, block)
-        big = b.populations(0).reshape(9, ny, 4)
-        small = b.populations(1).reshape(37, 50, 4)
-    worst = 0.0
-    for (lat, N, tau, (nx, n_y), _), f in ((inst[0], big), (inst[1], small)):
+        pops = [b.populations(i).reshape(-1, n_y, nx) for i, (_, _, _, (nx, n_y), _) in enumerate(inst)]
+    for (lat, N, tau, (nx, n_y), _), f in zip(inst, pops):
+        worst = 0.0
         ref_amp, ref_f = _oracle_column_run((lat, N, tau, n_y, A0, steps, steps))
         ref_f = ref_f[perm(lat)]
         for a in range(f.shape[0]):                  # one population at a time (the big one is 4.8 GB)
             worst = max(worst, float(np.max(np.abs(f[a] - ref_f[a][:, None]) / np.abs(ref_f[a][:, None]))))
-        da = float(np.max(np.abs(amp[inst.index((lat, N, tau, (nx, n_y), A0))] - ref_amp))) / A0
+        da = float(np.max(np.abs(amp[[q[0] for q in inst].index(lat)] - ref_amp))) / A0
         say(f"batch form {form}/{block} {lat} {nx}x{n_y} FP64: pops {worst:.2e}, |dA|/A0 {da:.2e}")
         assert worst <= 1e-12 and da <= 1e-12
 
