@@ -136,8 +136,13 @@ __global__ __launch_bounds__(BLOCK) void k_shift_rows(StepArgs a) {
     if constexpr (F) Gx = (T)(a.force_g * a.force_cos[jf]);
     double sig_sum = 0.0;
     for (uint32_t k = 0; k < a.tile; ++k) {
-        const int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
+        int x = (int)((xb * a.tile + k) * BLOCK + threadIdx.x);
         if (x >= nx) break;
+        // 16-bit storages: the column is opaque to the optimiser, so the per-population load
+        // offsets are formed inside the loop from it (one add each, as they are anyway) instead
+        // of being hoisted as 64-bit addresses that hold registers through the collision.  The
+        // empty statement emits no instruction.
+        if constexpr (C::lowp) asm volatile("" : "+v"(x));
         raw rv[L::Q];
         static_for<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
